@@ -1,0 +1,204 @@
+/*
+ * nnp.h - C ABI of the MI355X (gfx950) Behler-Parrinello neural-network
+ * potential: energy, per-atom energies and forces of periodic orthorhombic
+ * structures, and the parameter gradient of an energy+force training loss.
+ *
+ * Method (Desai, Reeve, Belak, arXiv:2002.00054, Sec. 3.1 and Fig. 1(b)):
+ *   step 1  symmetry functions G_i of every atom i from its neighbours within
+ *           the cutoff rc: radial G2 (the step-1 formula of Fig. 1(b)) and the
+ *           narrow angular G3 of Behler (the paper's ref. [18]; Sec. 3.1 names
+ *           the angular loop over neighbours of neighbours without printing
+ *           it):
+ *             G2 = sum_j exp(-eta (r_ij - rs)^2) fc(r_ij)
+ *             G3 = 2^(1-zeta) sum_{j<k} (1 + lambda cos theta_ijk)^zeta
+ *                  exp(-eta (r_ij^2 + r_ik^2 + r_jk^2)) fc(r_ij) fc(r_ik) fc(r_jk)
+ *           with fc(r) = (cos(pi r / rc) + 1) / 2 for r < rc, else 0;
+ *   step 2  E_i = NN_{e_i}((G_i - shift) / scale), one feed-forward network per
+ *           element (Fig. 1(c)), tanh hidden layers, linear output;
+ *           E = sum_i E_i;
+ *   step 3  f_m = -dE/dr_m (the sign convention of Fig. 1(a),(b)) by the chain
+ *           rule through dE_i/dG_i and dG_i/dr_m.
+ *
+ * Units: Angstrom and eV.  Neighbours use the minimum image, which needs every
+ * box edge > 2 rc.  Positions may lie outside the box; they are wrapped.
+ *
+ * Threading: a handle may be used by one host thread and one stream at a time.
+ * All work of a call is enqueued on the caller's stream; calls that return a
+ * host value (the energy) or detect errors synchronise that stream.
+ */
+#ifndef NNP_H
+#define NNP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nnp_handle nnp_handle;
+
+typedef enum {
+  NNP_OK = 0,
+  NNP_E_ARG = -1,   /* invalid argument (null pointer, size, table entry)     */
+  NNP_E_BOX = -2,   /* some box edge <= 2 rc (minimum image undefined) or not finite */
+  NNP_E_TYPE = -3,  /* an atom type outside [0, n_el); outputs are undefined   */
+  NNP_E_HIP = -4,   /* a HIP runtime call failed                              */
+  NNP_E_NOMEM = -5, /* device allocation failed                               */
+  NNP_E_STATE = -6  /* handle misuse (e.g. backward before any forward)       */
+} nnp_status;
+
+/*
+ * Arithmetic forms of the whole path.
+ *  NNP_FP64        every step in double precision; positions, per-atom
+ *                  energies and forces are double.
+ *  NNP_FP32        every step in single precision (FP32 MFMA for the network
+ *                  layers); positions, per-atom energies and forces are float.
+ *  NNP_BF16_MIXED  precision form: symmetry-function terms in FP32 summed per
+ *                  atom in FP64; hidden network layer on BF16 MFMA with FP32
+ *                  accumulation; first layer (and its transpose in dE/dG) in
+ *                  split BF16x3 (x = hi + lo, products hi*hi + hi*lo + lo*hi);
+ *                  forces accumulated in FP64 and the energy summed in FP64.
+ *                  Positions, per-atom energies and forces are float.
+ */
+typedef enum { NNP_FP64 = 0, NNP_FP32 = 1, NNP_BF16_MIXED = 2 } nnp_precision;
+
+/* One symmetry function of the table (Sec. 3.1 step 1).
+ *  centre    element of the centre atom, in [0, n_el)
+ *  kind      2 = radial G2 (neighbour element nbr[0]);
+ *            3 = narrow angular G3 (unordered neighbour-element pair nbr[0], nbr[1])
+ *  eta       Gaussian exponent, A^-2, >= 0
+ *  rs        radial shift, A (G2 only; must be 0 for G3)
+ *  zeta      integer-valued exponent in [1, 64] (G3 only)
+ *  lambda    +1 or -1 (G3 only)
+ *  rc        cutoff radius, A; every entry of one table must use the same rc
+ *  shift, scale  centring/scaling: the network sees (G - shift) / scale, scale != 0
+ * The order of the entries of one centre element is the order of that
+ * element's network inputs. */
+typedef struct {
+  int centre;
+  int kind;
+  int nbr[2];
+  double eta, rs, zeta, lambda, rc, shift, scale;
+} nnp_sf;
+
+/* One element's network (Sec. 3.1 step 2, Fig. 1(c)).
+ *  n_layers  number of weight layers, 1..4
+ *  sizes     [n_layers + 1] widths: sizes[0] = number of SFs of the element,
+ *            sizes[n_layers] = 1, hidden widths <= 32
+ *  W[l]      row-major [sizes[l+1]][sizes[l]] (host)
+ *  b[l]      [sizes[l+1]] (host)
+ *  activation 0 = tanh on hidden layers, linear output (the only one supported) */
+typedef struct {
+  int n_layers;
+  const int* sizes;
+  const double* const* W;
+  const double* const* b;
+  int activation;
+} nnp_net;
+
+/*
+ * Create a potential.  Deep-copies every host array (the caller may free them
+ * afterwards) and uploads the parameters to the current HIP device.
+ *  n_el      number of elements, 1..4
+ *  elements  [n_el] element names (informational; index = type id), may be NULL
+ *  n_sf, sf  the symmetry-function table (see nnp_sf); per element at most 64
+ *            entries, per (centre, neighbour element) at most 16 radial, per
+ *            (centre, neighbour pair) at most 8 angular, and per centre at most
+ *            4 distinct angular eta
+ *  nets      [n_el] networks; nets[e].sizes[0] must equal the number of SFs of
+ *            centre element e
+ *  prec      arithmetic form
+ *  out       receives the handle (NULL on failure)
+ * Errors: NNP_E_ARG for a malformed table or network, NNP_E_HIP / NNP_E_NOMEM. */
+nnp_status nnp_create(int n_el, const char* const* elements, int n_sf, const nnp_sf* sf,
+                      const nnp_net* nets, nnp_precision prec, nnp_handle** out);
+
+/*
+ * Energy, per-atom energies and forces of one structure (Fig. 1(b) steps 1-3).
+ *  n_atoms      number of atoms, >= 0 (0 gives E = 0)
+ *  pos          device [n_atoms][3], double (NNP_FP64) or float (other forms)
+ *  types        device int32 [n_atoms], element ids in [0, n_el)
+ *  box          host double[3], orthorhombic edges; each must exceed 2 rc
+ *  energy       host, receives E = sum_i E_i (double); may be NULL
+ *  atom_energy  device [n_atoms] E_i in the positions' type; may be NULL
+ *  forces       device [n_atoms][3] f = -dE/dr in the positions' type; may be NULL
+ *  stream       hipStream_t (NULL = default stream)
+ * Outputs are in the caller's atom order.  The neighbour list is rebuilt on
+ * every call; if an atom has more neighbours than the current capacity the
+ * handle grows it and recomputes (not an error).  Synchronises the stream.
+ * Errors: NNP_E_ARG, NNP_E_BOX (checked before any launch), NNP_E_TYPE
+ * (detected on the device; reported by the same call), NNP_E_HIP, NNP_E_NOMEM. */
+nnp_status nnp_compute(nnp_handle* h, int64_t n_atoms, const void* pos, const int32_t* types,
+                       const double box[3], double* energy, void* atom_energy, void* forces,
+                       void* stream);
+
+/*
+ * The same for a batch of independent structures stored back to back.
+ *  n_struct      number of structures, >= 1
+ *  atom_offsets  host int64 [n_struct + 1], offsets[0] = 0, non-decreasing;
+ *                structure b holds atoms [offsets[b], offsets[b+1])
+ *  pos, types    device, all structures' atoms
+ *  boxes         host double [n_struct][3]
+ *  energies      device double [n_struct]; may be NULL
+ *  atom_energy, forces  as in nnp_compute (batch order); may be NULL
+ * Synchronises the stream. */
+nnp_status nnp_compute_batch(nnp_handle* h, int n_struct, const int64_t* atom_offsets, const void* pos,
+                             const int32_t* types, const double* boxes, double* energies,
+                             void* atom_energy, void* forces, void* stream);
+
+/*
+ * Differentiation form: gradient of a scalar loss L(E_b, F) with respect to
+ * every network parameter, given dL/dE_b and dL/dF of the batch evaluated by
+ * nnp_compute_batch with the same arguments:
+ *   dL/dtheta = sum_b dL/dE_b dE_b/dtheta + sum_m dL/dF_m . dF_m/dtheta.
+ * The descriptor derivatives are recomputed, not stored.
+ *  dL_dE        device double [n_struct] (may be NULL: no energy term)
+ *  dL_dF        device [n_atoms][3] in the positions' type (may be NULL: no force term)
+ *  grad_params  device double [nnp_n_params(h)], overwritten; flat layout of
+ *               nnp_set_params
+ * Synchronises the stream.  Errors as nnp_compute_batch. */
+nnp_status nnp_backward(nnp_handle* h, int n_struct, const int64_t* atom_offsets, const void* pos,
+                        const int32_t* types, const double* boxes, const double* dL_dE,
+                        const void* dL_dF, void* grad_params, void* stream);
+
+/* Number of network parameters: sum over elements and layers of out*in + out. */
+int64_t nnp_n_params(const nnp_handle* h);
+
+/*
+ * Replace every network parameter.  flat_params: double [nnp_n_params(h)],
+ * element by element, layer by layer, W row-major [out][in] then b[out];
+ * on_device != 0 if it is a device pointer (then the device is synchronised).
+ */
+nnp_status nnp_set_params(nnp_handle* h, const void* flat_params, int on_device);
+
+/* Copy the current parameters (same layout) into host memory. */
+nnp_status nnp_get_params(const nnp_handle* h, double* flat_params_host);
+
+/*
+ * Per-kernel timing of the last call on this handle, in milliseconds, from
+ * HIP events on the caller's stream, when enabled with nnp_set_profiling.
+ *  names: receives up to max_k static kernel-stage names; ms: their times.
+ * Returns the number of stages written.
+ */
+nnp_status nnp_set_profiling(nnp_handle* h, int enable);
+int nnp_last_timings(const nnp_handle* h, const char** names, double* ms, int max_k);
+
+/* Neighbour capacity (slots per atom) currently allocated. */
+int nnp_neighbor_capacity(const nnp_handle* h);
+
+/* Override the neighbour capacity (>= 8): the next call starts from it and
+ * regrows on overflow. */
+nnp_status nnp_set_neighbor_capacity(nnp_handle* h, int cap);
+
+/* Release the handle and all its device memory.  NULL is allowed. */
+void nnp_destroy(nnp_handle* h);
+
+/* Readable message of the last error on this handle ("" if none); with a NULL
+ * handle, the last error of nnp_create on this thread. */
+const char* nnp_last_error(const nnp_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NNP_H */

@@ -1,0 +1,855 @@
+// Host layer of the C ABI in include/nnp.h: argument checks, packing of the
+// SF table and networks into device blocks, the growable workspace, and the
+// kernel sequence of one call on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/nnp.h"
+#include "kernels.h"
+
+namespace nnp {
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+}  // namespace nnp
+
+struct nnp_handle {
+  int n_el = 0;
+  int prec = NNP_FP32;
+  int device = 0;
+  std::string err;
+  double rc = 0.0;
+  int ne_tmpl = 2;                      // template bound of distinct angular eta (2 or 4)
+  std::vector<int> n_sf;                // per element
+  std::vector<std::vector<int>> sizes;  // per element layer widths
+  std::vector<double> params;           // flat caller layout
+  std::vector<int> flatmap;             // flat index -> padded index
+  nnp::DevTab<double> tab_d;            // host copy (double)
+  // device parameter blocks
+  void* d_tab = nullptr;                // DevTab<T>
+  void* d_nets = nullptr;               // [n_el][NET_STRIDE] T
+  int* d_flatmap = nullptr;
+  // workspace
+  std::map<std::string, nnp::DevBuf> ws;
+  int cap = 0;                          // neighbour slots per atom
+  int cap_override = 0;
+  // pinned staging for small uploads / readbacks
+  void* h_stage = nullptr;
+  size_t h_stage_bytes = 0;
+  int* h_flags = nullptr;               // pinned [4]
+  double* h_energy = nullptr;           // pinned [1]
+  // profiling
+  bool prof = false;
+  std::vector<const char*> t_names;
+  std::vector<double> t_ms;
+  std::vector<hipEvent_t> events;
+  bool has_forward = false;
+};
+
+namespace nnp {
+namespace {
+
+nnp_status fail(nnp_handle* h, nnp_status st, const std::string& msg) {
+  if (h) h->err = msg;
+  else g_create_error = msg;
+  return st;
+}
+
+#define NNP_HIP(h, call)                                                                             \
+  do {                                                                                                \
+    hipError_t e_ = (call);                                                                           \
+    if (e_ != hipSuccess)                                                                             \
+      return fail(h, e_ == hipErrorOutOfMemory ? NNP_E_NOMEM : NNP_E_HIP,                             \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                                 \
+  } while (0)
+
+// Error of the last launches on this thread, if any.
+nnp_status check_launch(nnp_handle* h, const char* stage) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(h, NNP_E_HIP, std::string(stage) + ": " + hipGetErrorString(e));
+  return NNP_OK;
+}
+
+// Largest dynamic LDS a workgroup may use on the current device.
+size_t lds_limit() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) return 65536;
+  return (size_t)v;
+}
+
+// Grow-only named device buffer.
+nnp_status ensure(nnp_handle* h, const char* name, size_t bytes, void** out) {
+  DevBuf& b = h->ws[name];
+  if (b.bytes < bytes) {
+    if (b.p) {
+      hipError_t e = hipFree(b.p);
+      b.p = nullptr;
+      b.bytes = 0;
+      if (e != hipSuccess) return fail(h, NNP_E_HIP, std::string("hipFree: ") + hipGetErrorString(e));
+    }
+    size_t nb = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&b.p, nb);
+    if (e != hipSuccess) {
+      b.p = nullptr;
+      return fail(h, NNP_E_NOMEM, std::string("hipMalloc(") + name + ", " + std::to_string(nb) + "): " +
+                                      hipGetErrorString(e));
+    }
+    b.bytes = nb;
+  }
+  *out = b.p;
+  return NNP_OK;
+}
+
+template <class X>
+nnp_status ensure_t(nnp_handle* h, const char* name, size_t count, X** out) {
+  void* p = nullptr;
+  nnp_status st = ensure(h, name, count * sizeof(X), &p);
+  *out = reinterpret_cast<X*>(p);
+  return st;
+}
+
+nnp_status stage(nnp_handle* h, size_t bytes) {
+  if (h->h_stage_bytes >= bytes) return NNP_OK;
+  if (h->h_stage) (void)hipHostFree(h->h_stage);
+  h->h_stage = nullptr;
+  h->h_stage_bytes = 0;
+  NNP_HIP(h, hipHostMalloc(&h->h_stage, std::max<size_t>(bytes, 4096), hipHostMallocDefault));
+  h->h_stage_bytes = std::max<size_t>(bytes, 4096);
+  return NNP_OK;
+}
+
+// Taylor coefficients in s = r^2 of fc = (1 + cos(pi sqrt(s)/rc))/2 and of dfc/ds.
+void cutoff_coefficients(double rc, double* c, double* d, int deg_max) {
+  long double a = 1.0L;  // (pi/rc)^(2n) / (2n)!
+  const long double q = (long double)M_PI / (long double)rc;
+  std::vector<long double> f(deg_max + 2, 0.0L);
+  f[0] = 1.0L;
+  for (int n = 1; n <= deg_max + 1; ++n) {
+    a *= q * q / ((long double)(2 * n - 1) * (long double)(2 * n));
+    f[n] = 0.5L * ((n & 1) ? -a : a);
+  }
+  for (int n = 0; n <= deg_max; ++n) {
+    c[n] = (double)f[n];
+    d[n] = (double)((long double)(n + 1) * f[n + 1]);
+  }
+}
+
+template <class T>
+DevTab<T> convert_tab(const DevTab<double>& s) {
+  DevTab<T> t;
+  std::memset(&t, 0, sizeof(t));
+  t.n_el = s.n_el;
+  for (int e = 0; e < MAX_EL; ++e) t.n_sf[e] = s.n_sf[e];
+  t.rc2 = (T)s.rc2;
+  for (int n = 0; n <= FC_DEG_MAX; ++n) {
+    t.fc_c[n] = (T)s.fc_c[n];
+    t.fc_d[n] = (T)s.fc_d[n];
+  }
+  for (int e = 0; e < MAX_EL; ++e) {
+    for (int f = 0; f < MAX_EL; ++f) {
+      t.rad_cnt[e][f] = s.rad_cnt[e][f];
+      for (int k = 0; k < MAX_RAD; ++k) {
+        t.rad_eta[e][f][k] = (T)s.rad_eta[e][f][k];
+        t.rad_rs[e][f][k] = (T)s.rad_rs[e][f][k];
+        t.rad_out[e][f][k] = s.rad_out[e][f][k];
+      }
+    }
+    t.n_eta[e] = s.n_eta[e];
+    for (int n = 0; n < MAX_NE; ++n) {
+      t.aeta[e][n] = (T)s.aeta[e][n];
+      t.aeta2[e][n] = (T)s.aeta2[e][n];
+    }
+    for (int c = 0; c < MAX_CLS; ++c) {
+      t.ang_cnt[e][c] = s.ang_cnt[e][c];
+      for (int k = 0; k < MAX_ANG; ++k) {
+        t.ang_eta[e][c][k] = s.ang_eta[e][c][k];
+        t.ang_zeta[e][c][k] = s.ang_zeta[e][c][k];
+        t.ang_lam[e][c][k] = s.ang_lam[e][c][k];
+        t.ang_pre[e][c][k] = (T)s.ang_pre[e][c][k];
+        t.ang_out[e][c][k] = s.ang_out[e][c][k];
+      }
+    }
+    for (int k = 0; k < MAX_SF; ++k) {
+      t.shift_d[e][k] = s.shift_d[e][k];
+      t.inv_scale_d[e][k] = s.inv_scale_d[e][k];
+    }
+  }
+  return t;
+}
+
+// Upload the padded networks (type T) from the flat caller layout.
+template <class T>
+nnp_status upload_nets(nnp_handle* h) {
+  std::vector<T> pad((size_t)h->n_el * NET_STRIDE, T(0));
+  for (size_t i = 0; i < h->params.size(); ++i) pad[h->flatmap[i]] = (T)h->params[i];
+  if (!h->d_nets) NNP_HIP(h, hipMalloc(&h->d_nets, pad.size() * sizeof(T)));
+  NNP_HIP(h, hipMemcpy(h->d_nets, pad.data(), pad.size() * sizeof(T), hipMemcpyHostToDevice));
+  return NNP_OK;
+}
+
+nnp_status upload_params(nnp_handle* h) {
+  if (h->prec == NNP_FP64) return upload_nets<double>(h);
+  return upload_nets<float>(h);
+}
+
+// ------------------------------------------------------------------ batch
+struct Batch {
+  int n_struct = 0;
+  int64_t n = 0;
+  std::vector<DevStruct> st;
+  std::vector<int64_t> soff;
+  int total_cells = 0;
+  std::vector<int64_t> chunk_lo, chunk_hi;
+  std::vector<int> struct_chunk;
+};
+
+nnp_status make_batch(nnp_handle* h, int n_struct, const int64_t* offs, const double* boxes, Batch& B) {
+  if (n_struct < 1) return fail(h, NNP_E_ARG, "n_struct must be >= 1");
+  if (!offs || !boxes) return fail(h, NNP_E_ARG, "atom_offsets and boxes must not be NULL");
+  if (offs[0] != 0) return fail(h, NNP_E_ARG, "atom_offsets[0] must be 0");
+  B.n_struct = n_struct;
+  B.soff.assign(offs, offs + n_struct + 1);
+  B.n = offs[n_struct];
+  if (B.n > (int64_t)INT32_MAX / 2) return fail(h, NNP_E_ARG, "too many atoms");
+  int64_t cells = 0;
+  const int64_t chunk = 4096;
+  for (int b = 0; b < n_struct; ++b) {
+    if (offs[b + 1] < offs[b]) return fail(h, NNP_E_ARG, "atom_offsets must be non-decreasing");
+    DevStruct s;
+    std::memset(&s, 0, sizeof(s));
+    const int64_t nb = offs[b + 1] - offs[b];
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+      const double L = boxes[3 * b + a];
+      if (!std::isfinite(L) || !(L > 2.0 * h->rc))
+        return fail(h, NNP_E_BOX, "box edge " + std::to_string(L) + " of structure " + std::to_string(b) +
+                                      " must be finite and exceed 2 rc = " + std::to_string(2.0 * h->rc));
+      s.L[a] = L;
+      s.invL[a] = 1.0 / L;
+      s.ncell[a] = std::max(1, (int)std::floor(L / h->rc));
+      ncell *= s.ncell[a];
+    }
+    // Bound the cell count of sparse boxes: coarser cells stay >= rc.
+    const int64_t limit = std::max<int64_t>(64, 8 * nb);
+    while (ncell > limit) {
+      ncell = 1;
+      for (int a = 0; a < 3; ++a) {
+        s.ncell[a] = std::max(1, s.ncell[a] / 2);
+        ncell *= s.ncell[a];
+      }
+    }
+    s.cellbase = (int)cells;
+    s.off = offs[b];
+    s.n = nb;
+    cells += ncell;
+    if (cells * h->n_el > (int64_t)1 << 28) return fail(h, NNP_E_ARG, "too many cells");
+    B.st.push_back(s);
+    B.struct_chunk.push_back((int)B.chunk_lo.size());
+    for (int64_t c0 = offs[b]; c0 < offs[b + 1]; c0 += chunk) {
+      B.chunk_lo.push_back(c0);
+      B.chunk_hi.push_back(std::min(offs[b + 1], c0 + chunk));
+    }
+  }
+  B.struct_chunk.push_back((int)B.chunk_lo.size());
+  B.total_cells = (int)cells;
+  return NNP_OK;
+}
+
+// Profiling marks on the caller's stream.
+struct Marks {
+  nnp_handle* h;
+  hipStream_t s;
+  int k = 0;
+  Marks(nnp_handle* h_, hipStream_t s_) : h(h_), s(s_) {
+    h->t_names.clear();
+    h->t_ms.clear();
+    if (h->prof) mark(nullptr);
+  }
+  void mark(const char* name) {
+    if (!h->prof) return;
+    if ((int)h->events.size() <= k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      h->events.push_back(e);
+    }
+    (void)hipEventRecord(h->events[k], s);
+    if (name) h->t_names.push_back(name);
+    ++k;
+  }
+  void finish() {
+    if (!h->prof) return;
+    for (int i = 0; i + 1 < k && i < (int)h->t_names.size(); ++i) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, h->events[i], h->events[i + 1]);
+      h->t_ms.push_back(ms);
+    }
+  }
+};
+
+// Neighbour capacity from the densest structure: mean count * 1.2 + 16,
+// rounded up to a multiple of 16 (a denser spot triggers a regrow).
+int initial_cap(nnp_handle* h, const Batch& B) {
+  if (h->cap_override) return h->cap_override;
+  double rho = 0.0;
+  for (const auto& s : B.st) rho = std::max(rho, (double)s.n / (s.L[0] * s.L[1] * s.L[2]));
+  const double mean = rho * 4.0 / 3.0 * M_PI * h->rc * h->rc * h->rc;
+  int cap = (int)std::ceil(mean * 1.2 + 16.0);
+  cap = (cap + 15) / 16 * 16;
+  return std::max(cap, std::max(h->cap, 32));
+}
+
+struct Common {
+  Batch B;
+  int64_t* d_soff = nullptr;
+  DevStruct* d_st = nullptr;
+  int64_t* d_clo = nullptr;
+  int64_t* d_chi = nullptr;
+  int* d_sc = nullptr;
+  BinArgs bin;
+  int* nbr = nullptr;
+  int4* nnb = nullptr;
+};
+
+// Uploads the batch description and runs wrap + bin + counting sort.
+template <class IO>
+nnp_status prepare(nnp_handle* h, Common& cm, const IO* pos, const int32_t* types, hipStream_t stream) {
+  Batch& B = cm.B;
+  const int64_t n = B.n;
+  const int nkeys = h->n_el * B.total_cells;
+  nnp_status st;
+  const size_t nst = B.st.size(), nso = B.soff.size(), nch = B.chunk_lo.size(), nsc = B.struct_chunk.size();
+  if ((st = ensure_t(h, "st", nst, &cm.d_st))) return st;
+  if ((st = ensure_t(h, "soff", nso, &cm.d_soff))) return st;
+  if ((st = ensure_t(h, "clo", std::max<size_t>(nch, 1), &cm.d_clo))) return st;
+  if ((st = ensure_t(h, "chi", std::max<size_t>(nch, 1), &cm.d_chi))) return st;
+  if ((st = ensure_t(h, "sc", nsc, &cm.d_sc))) return st;
+  const size_t bytes = nst * sizeof(DevStruct) + (nso + 2 * nch) * sizeof(int64_t) + nsc * sizeof(int) + 64;
+  if ((st = stage(h, bytes))) return st;
+  unsigned char* hs = (unsigned char*)h->h_stage;
+  size_t o = 0;
+  auto put = [&](void* dst, const void* src, size_t nbytes) -> hipError_t {
+    std::memcpy(hs + o, src, nbytes);
+    hipError_t e = hipMemcpyAsync(dst, hs + o, nbytes, hipMemcpyHostToDevice, stream);
+    o += (nbytes + 15) & ~(size_t)15;
+    return e;
+  };
+  NNP_HIP(h, put(cm.d_st, B.st.data(), nst * sizeof(DevStruct)));
+  NNP_HIP(h, put(cm.d_soff, B.soff.data(), nso * sizeof(int64_t)));
+  if (nch) {
+    NNP_HIP(h, put(cm.d_clo, B.chunk_lo.data(), nch * sizeof(int64_t)));
+    NNP_HIP(h, put(cm.d_chi, B.chunk_hi.data(), nch * sizeof(int64_t)));
+  }
+  NNP_HIP(h, put(cm.d_sc, B.struct_chunk.data(), nsc * sizeof(int)));
+
+  BinArgs& a = cm.bin;
+  a.n = n;
+  a.types = types;
+  a.st = cm.d_st;
+  a.soff = cm.d_soff;
+  a.n_struct = B.n_struct;
+  a.n_el = h->n_el;
+  a.total_cells = B.total_cells;
+  if ((st = ensure_t(h, "key", std::max<int64_t>(n, 1), &a.key))) return st;
+  if ((st = ensure_t(h, "count", nkeys + 1, &a.count))) return st;
+  if ((st = ensure_t(h, "start", nkeys + 1, &a.start))) return st;
+  if ((st = ensure_t(h, "cursor", nkeys + 1, &a.cursor))) return st;
+  if ((st = ensure_t(h, "perm", std::max<int64_t>(n, 1), &a.perm))) return st;
+  if ((st = ensure_t(h, "pos4", std::max<int64_t>(n, 1), &a.pos4))) return st;
+  if ((st = ensure_t(h, "eoff", MAX_EL + 1, &a.eoff))) return st;
+  if ((st = ensure_t(h, "flags", 4, &a.flags))) return st;
+  launch_fill_int(a.flags, 4, 0, stream);
+  launch_bin_sort<IO>(a, pos, stream);
+  return NNP_OK;
+}
+
+nnp_status build_neighbors(nnp_handle* h, Common& cm, hipStream_t stream) {
+  nnp_status st;
+  const int64_t n = std::max<int64_t>(cm.B.n, 1);
+  if ((st = ensure_t(h, "nbr", (size_t)n * h->cap, &cm.nbr))) return st;
+  if ((st = ensure_t(h, "nnb", n, &cm.nnb))) return st;
+  launch_fill_int(cm.bin.flags + 1, 1, 0, stream);
+  launch_neighbors(cm.bin, h->rc, h->cap, cm.nbr, cm.nnb, stream);
+  return NNP_OK;
+}
+
+template <int P>
+TripArgs<P> trip_args(nnp_handle* h, Common& cm) {
+  TripArgs<P> t;
+  std::memset(&t, 0, sizeof(t));
+  t.n = cm.B.n;
+  t.cap = h->cap;
+  t.pos4 = cm.bin.pos4;
+  t.nbr = cm.nbr;
+  t.nnb = cm.nnb;
+  t.st = cm.d_st;
+  t.tab = reinterpret_cast<const DevTab<typename Types<P>::T>*>(h->d_tab);
+  return t;
+}
+
+// Reads back the flags; returns 1 if the neighbour capacity overflowed (cap
+// has been grown), 0 if all is well, <0 on error.
+int check_flags(nnp_handle* h, hipStream_t stream, Common& cm, nnp_status* st) {
+  hipError_t e = hipMemcpyAsync(h->h_flags, cm.bin.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    *st = fail(h, NNP_E_HIP, std::string("readback: ") + hipGetErrorString(e));
+    return -1;
+  }
+  if (h->h_flags[0]) {
+    *st = fail(h, NNP_E_TYPE, "atom type outside [0, n_el)");
+    return -1;
+  }
+  if (h->h_flags[1] > h->cap) {
+    int nc = (int)std::ceil(h->h_flags[1] * 1.15) + 8;
+    h->cap = (nc + 15) / 16 * 16;
+    return 1;
+  }
+  return 0;
+}
+
+template <int P>
+nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void* pos_v, const int32_t* types,
+                   const double* boxes, double* energies_dev, double* energy_host, void* ei_v, void* f_v,
+                   hipStream_t stream) {
+  using T = typename Types<P>::T;
+  using IO = typename Types<P>::IO;
+  using FAcc = typename Types<P>::FAcc;
+  Common cm;
+  nnp_status st;
+  if ((st = make_batch(h, n_struct, offs, boxes, cm.B))) return st;
+  const int64_t n = cm.B.n;
+  if (n > 0 && (!pos_v || !types)) return fail(h, NNP_E_ARG, "pos and types must not be NULL");
+  const IO* pos = reinterpret_cast<const IO*>(pos_v);
+  h->cap = initial_cap(h, cm.B);
+  Marks mk(h, stream);
+  (void)hipGetLastError();
+  if ((st = prepare<IO>(h, cm, pos, types, stream))) return st;
+  mk.mark("bin_sort");
+  IO *G, *C, *Ei_s;
+  FAcc* F_s;
+  double *Ei_o, *partial, *energies;
+  const int64_t n1 = std::max<int64_t>(n, 1);
+  if ((st = ensure_t(h, "G", (size_t)n1 * LD, &G))) return st;
+  if ((st = ensure_t(h, "C", (size_t)n1 * LD, &C))) return st;
+  if ((st = ensure_t(h, "Ei_s", n1, &Ei_s))) return st;
+  if ((st = ensure_t(h, "F_s", (size_t)n1 * 3, &F_s))) return st;
+  if ((st = ensure_t(h, "Ei_o", n1, &Ei_o))) return st;
+  if ((st = ensure_t(h, "partial", std::max<size_t>(cm.B.chunk_lo.size(), 1), &partial))) return st;
+  if ((st = ensure_t(h, "energies", n_struct, &energies))) return st;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    if ((st = build_neighbors(h, cm, stream))) return st;
+    mk.mark("neighbors");
+    TripArgs<P> ta = trip_args<P>(h, cm);
+    const size_t lds = triplet_lds_bytes<P>(1, h->ne_tmpl, h->cap);
+    if (lds > lds_limit())
+      return fail(h, NNP_E_ARG, "neighbour capacity " + std::to_string(h->cap) + " needs " + std::to_string(lds) +
+                                    " bytes of LDS per workgroup, more than the device allows");
+    ta.G = G;
+    launch_triplet<P>(0, h->ne_tmpl, ta, stream);
+    mk.mark("sf");
+    MlpArgs<P> ma;
+    std::memset(&ma, 0, sizeof(ma));
+    ma.n = n;
+    ma.n_el = h->n_el;
+    ma.eoff = cm.bin.eoff;
+    ma.G = G;
+    ma.C = C;
+    ma.Ei = Ei_s;
+    ma.nets = reinterpret_cast<const T*>(h->d_nets);
+    ma.tab = ta.tab;
+    launch_mlp<P>(ma, stream);
+    mk.mark("mlp");
+    launch_fill<FAcc>(F_s, n * 3, FAcc(0), stream);
+    ta.C = C;
+    ta.F = F_s;
+    launch_triplet<P>(1, h->ne_tmpl, ta, stream);
+    mk.mark("force");
+    launch_unpermute<IO, FAcc>(n, cm.bin.perm, Ei_s, F_s, Ei_o, reinterpret_cast<IO*>(ei_v),
+                               reinterpret_cast<IO*>(f_v), stream);
+    launch_energy(Ei_o, cm.d_clo, cm.d_chi, (int)cm.B.chunk_lo.size(), cm.d_sc, n_struct, partial, energies, stream);
+    if (energies_dev)
+      NNP_HIP(h, hipMemcpyAsync(energies_dev, energies, n_struct * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    if (energy_host)
+      NNP_HIP(h, hipMemcpyAsync(h->h_energy, energies, sizeof(double), hipMemcpyDeviceToHost, stream));
+    mk.mark("finish");
+    if ((st = check_launch(h, "forward"))) return st;
+    const int r = check_flags(h, stream, cm, &st);
+    if (r < 0) return st;
+    if (r == 0) {
+      if (energy_host) *energy_host = *h->h_energy;
+      mk.finish();
+      h->has_forward = true;
+      return NNP_OK;
+    }
+    // capacity grew: rebuild the neighbour list and redo the evaluation
+  }
+  return fail(h, NNP_E_STATE, "neighbour capacity did not converge");
+}
+
+template <int P>
+nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void* pos_v, const int32_t* types,
+                    const double* boxes, const double* dL_dE, const void* dL_dF_v, double* grad, hipStream_t stream) {
+  using T = typename Types<P>::T;
+  using IO = typename Types<P>::IO;
+  Common cm;
+  nnp_status st;
+  if ((st = make_batch(h, n_struct, offs, boxes, cm.B))) return st;
+  const int64_t n = cm.B.n;
+  if (n > 0 && (!pos_v || !types)) return fail(h, NNP_E_ARG, "pos and types must not be NULL");
+  if (!grad) return fail(h, NNP_E_ARG, "grad_params must not be NULL");
+  const IO* pos = reinterpret_cast<const IO*>(pos_v);
+  const IO* dLdF = reinterpret_cast<const IO*>(dL_dF_v);
+  h->cap = initial_cap(h, cm.B);
+  Marks mk(h, stream);
+  (void)hipGetLastError();
+  if ((st = prepare<IO>(h, cm, pos, types, stream))) return st;
+  mk.mark("bin_sort");
+  IO *G, *V, *delta;
+  double *gE_atom, *part, *padded;
+  T* vec;
+  const int64_t n1 = std::max<int64_t>(n, 1);
+  const int chunk = 256;
+  const int nch = (int)((n1 + chunk - 1) / chunk);
+  if ((st = ensure_t(h, "G", (size_t)n1 * LD, &G))) return st;
+  if ((st = ensure_t(h, "V", (size_t)n1 * LD, &V))) return st;
+  if ((st = ensure_t(h, "delta", (size_t)n1 * 3, &delta))) return st;
+  if ((st = ensure_t(h, "gE_atom", n1, &gE_atom))) return st;
+  if ((st = ensure_t(h, "wvec", (size_t)n1 * 11 * HID, &vec))) return st;
+  if ((st = ensure_t(h, "wpart", (size_t)h->n_el * nch * NET_STRIDE, &part))) return st;
+  if ((st = ensure_t(h, "wpad", (size_t)h->n_el * NET_STRIDE, &padded))) return st;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    if ((st = build_neighbors(h, cm, stream))) return st;
+    mk.mark("neighbors");
+    TripArgs<P> ta = trip_args<P>(h, cm);
+    if (triplet_lds_bytes<P>(2, h->ne_tmpl, h->cap) > lds_limit())
+      return fail(h, NNP_E_ARG, "neighbour capacity " + std::to_string(h->cap) + " needs more LDS than the device allows");
+    ta.G = G;
+    launch_triplet<P>(0, h->ne_tmpl, ta, stream);
+    mk.mark("sf");
+    if (dLdF) launch_permute_rows3<IO>(n, cm.bin.perm, dLdF, delta, stream);
+    else launch_fill<IO>(delta, n * 3, IO(0), stream);
+    ta.delta = delta;
+    ta.V = V;
+    launch_triplet<P>(2, h->ne_tmpl, ta, stream);
+    mk.mark("jvp");
+    launch_gather_struct_grad(n, cm.bin.perm, cm.d_soff, n_struct, dL_dE, gE_atom, stream);
+    WGradArgs<P> wa;
+    std::memset(&wa, 0, sizeof(wa));
+    wa.n = n;
+    wa.n_el = h->n_el;
+    wa.eoff = cm.bin.eoff;
+    wa.G = G;
+    wa.V = V;
+    wa.gE_atom = gE_atom;
+    wa.nets = reinterpret_cast<const T*>(h->d_nets);
+    wa.tab = ta.tab;
+    wa.vec = vec;
+    wa.chunk = chunk;
+    wa.nch = nch;
+    wa.partial = part;
+    wa.padded = padded;
+    wa.n_params = (int64_t)h->params.size();
+    wa.flatmap = h->d_flatmap;
+    wa.out = grad;
+    launch_wgrad<P>(wa, stream);
+    mk.mark("wgrad");
+    if ((st = check_launch(h, "backward"))) return st;
+    const int r = check_flags(h, stream, cm, &st);
+    if (r < 0) return st;
+    if (r == 0) {
+      mk.finish();
+      return NNP_OK;
+    }
+  }
+  return fail(h, NNP_E_STATE, "neighbour capacity did not converge");
+}
+
+// --------------------------------------------------------------- create
+nnp_status build_table(nnp_handle* h, int n_el, int n_sf, const nnp_sf* sf, const nnp_net* nets) {
+  DevTab<double>& t = h->tab_d;
+  std::memset(&t, 0, sizeof(t));
+  t.n_el = n_el;
+  h->rc = 0.0;
+  std::vector<std::vector<double>> etas(n_el);
+  std::vector<int> count(n_el, 0);
+  for (int s = 0; s < n_sf; ++s) {
+    const nnp_sf& d = sf[s];
+    const std::string at = "sf[" + std::to_string(s) + "]: ";
+    if (d.centre < 0 || d.centre >= n_el) return fail(nullptr, NNP_E_ARG, at + "centre out of range");
+    if (d.kind != 2 && d.kind != 3) return fail(nullptr, NNP_E_ARG, at + "kind must be 2 or 3");
+    if (d.nbr[0] < 0 || d.nbr[0] >= n_el) return fail(nullptr, NNP_E_ARG, at + "nbr[0] out of range");
+    if (d.kind == 3 && (d.nbr[1] < 0 || d.nbr[1] >= n_el)) return fail(nullptr, NNP_E_ARG, at + "nbr[1] out of range");
+    if (!std::isfinite(d.eta) || d.eta < 0) return fail(nullptr, NNP_E_ARG, at + "eta must be finite and >= 0");
+    if (!std::isfinite(d.rc) || d.rc <= 0) return fail(nullptr, NNP_E_ARG, at + "rc must be > 0");
+    if (h->rc == 0.0) h->rc = d.rc;
+    if (d.rc != h->rc) return fail(nullptr, NNP_E_ARG, at + "all SFs must share one rc");
+    if (!std::isfinite(d.scale) || d.scale == 0.0 || !std::isfinite(d.shift))
+      return fail(nullptr, NNP_E_ARG, at + "shift must be finite and scale finite and non-zero");
+    const int e = d.centre;
+    const int k = count[e]++;
+    if (k >= MAX_SF) return fail(nullptr, NNP_E_ARG, at + "more than 32 SFs for one element");
+    t.shift_d[e][k] = d.shift;
+    t.inv_scale_d[e][k] = 1.0 / d.scale;
+    if (d.kind == 2) {
+      if (!std::isfinite(d.rs)) return fail(nullptr, NNP_E_ARG, at + "rs must be finite");
+      const int f = d.nbr[0];
+      const int q = t.rad_cnt[e][f]++;
+      if (q >= MAX_RAD) return fail(nullptr, NNP_E_ARG, at + "more than 16 radial SFs for one element pair");
+      t.rad_eta[e][f][q] = d.eta;
+      t.rad_rs[e][f][q] = d.rs;
+      t.rad_out[e][f][q] = k;
+    } else {
+      if (d.rs != 0.0) return fail(nullptr, NNP_E_ARG, at + "rs must be 0 for angular SFs");
+      if (d.zeta != std::floor(d.zeta) || d.zeta < 1 || d.zeta > 64)
+        return fail(nullptr, NNP_E_ARG, at + "zeta must be an integer in [1, 64]");
+      if (d.lambda != 1.0 && d.lambda != -1.0) return fail(nullptr, NNP_E_ARG, at + "lambda must be +1 or -1");
+      const int e1 = std::min(d.nbr[0], d.nbr[1]), e2 = std::max(d.nbr[0], d.nbr[1]);
+      const int cls = class_index(e1, e2, n_el);
+      const int q = t.ang_cnt[e][cls]++;
+      if (q >= MAX_ANG) return fail(nullptr, NNP_E_ARG, at + "more than 8 angular SFs for one neighbour pair");
+      int ei = -1;
+      for (size_t x = 0; x < etas[e].size(); ++x)
+        if (etas[e][x] == d.eta) ei = (int)x;
+      if (ei < 0) {
+        if ((int)etas[e].size() >= MAX_NE)
+          return fail(nullptr, NNP_E_ARG, at + "more than 4 distinct angular eta for one element");
+        ei = (int)etas[e].size();
+        etas[e].push_back(d.eta);
+      }
+      t.ang_eta[e][cls][q] = ei;
+      t.ang_zeta[e][cls][q] = (int)d.zeta;
+      t.ang_lam[e][cls][q] = d.lambda > 0 ? 1 : -1;
+      t.ang_pre[e][cls][q] = std::pow(2.0, 1.0 - d.zeta);
+      t.ang_out[e][cls][q] = k;
+    }
+  }
+  int ne_max = 1;
+  for (int e = 0; e < n_el; ++e) {
+    t.n_sf[e] = count[e];
+    t.n_eta[e] = (int)etas[e].size();
+    for (size_t x = 0; x < etas[e].size(); ++x) {
+      t.aeta[e][x] = etas[e][x];
+      t.aeta2[e][x] = etas[e][x] * 1.4426950408889634074;
+    }
+    ne_max = std::max(ne_max, t.n_eta[e]);
+  }
+  h->ne_tmpl = ne_max <= 2 ? 2 : 4;
+  t.rc2 = h->rc * h->rc;
+  cutoff_coefficients(h->rc, t.fc_c, t.fc_d, FC_DEG_MAX);
+  h->n_sf = count;
+  // networks
+  h->sizes.clear();
+  h->params.clear();
+  h->flatmap.clear();
+  for (int e = 0; e < n_el; ++e) {
+    const nnp_net& nt = nets[e];
+    const std::string at = "nets[" + std::to_string(e) + "]: ";
+    if (nt.n_layers != 3) return fail(nullptr, NNP_E_ARG, at + "exactly two hidden layers (n_layers = 3) are supported");
+    if (!nt.sizes || !nt.W || !nt.b) return fail(nullptr, NNP_E_ARG, at + "NULL sizes/W/b");
+    if (nt.activation != 0) return fail(nullptr, NNP_E_ARG, at + "only activation 0 (tanh) is supported");
+    std::vector<int> sz(nt.sizes, nt.sizes + 4);
+    if (sz[0] != count[e]) return fail(nullptr, NNP_E_ARG, at + "sizes[0] must equal the element's SF count");
+    if (sz[3] != 1) return fail(nullptr, NNP_E_ARG, at + "output width must be 1");
+    if (sz[1] < 1 || sz[1] > HID || sz[2] < 1 || sz[2] > HID)
+      return fail(nullptr, NNP_E_ARG, at + "hidden widths must be in [1, 32]");
+    const int offW[3] = {OFF_W1, OFF_W2, OFF_W3}, offB[3] = {OFF_B1, OFF_B2, OFF_B3};
+    for (int l = 0; l < 3; ++l) {
+      if (!nt.W[l] || !nt.b[l]) return fail(nullptr, NNP_E_ARG, at + "NULL layer array");
+      for (int o = 0; o < sz[l + 1]; ++o)
+        for (int i = 0; i < sz[l]; ++i) {
+          const double w = nt.W[l][(size_t)o * sz[l] + i];
+          if (!std::isfinite(w)) return fail(nullptr, NNP_E_ARG, at + "non-finite weight");
+          h->params.push_back(w);
+          h->flatmap.push_back(e * NET_STRIDE + (l < 2 ? offW[l] + o * HID + i : offW[l] + i));
+        }
+      for (int o = 0; o < sz[l + 1]; ++o) {
+        const double bv = nt.b[l][o];
+        if (!std::isfinite(bv)) return fail(nullptr, NNP_E_ARG, at + "non-finite bias");
+        h->params.push_back(bv);
+        h->flatmap.push_back(e * NET_STRIDE + offB[l] + o);
+      }
+    }
+    h->sizes.push_back(sz);
+  }
+  return NNP_OK;
+}
+
+}  // namespace
+}  // namespace nnp
+
+using namespace nnp;
+
+extern "C" {
+
+nnp_status nnp_create(int n_el, const char* const* elements, int n_sf, const nnp_sf* sf, const nnp_net* nets,
+                      nnp_precision prec, nnp_handle** out) {
+  (void)elements;
+  g_create_error.clear();
+  if (!out) return fail(nullptr, NNP_E_ARG, "out must not be NULL");
+  *out = nullptr;
+  if (n_el < 1 || n_el > MAX_EL) return fail(nullptr, NNP_E_ARG, "n_el must be in [1, 4]");
+  if (n_sf < 1 || !sf || !nets) return fail(nullptr, NNP_E_ARG, "empty SF table or NULL nets");
+  if (prec != NNP_FP64 && prec != NNP_FP32 && prec != NNP_BF16_MIXED) return fail(nullptr, NNP_E_ARG, "bad precision");
+  nnp_handle* h = new nnp_handle();
+  h->n_el = n_el;
+  h->prec = prec;
+  nnp_status st = build_table(h, n_el, n_sf, sf, nets);
+  if (st) {
+    delete h;
+    return st;
+  }
+  auto bail = [&](nnp_status s) {
+    g_create_error = h->err;
+    nnp_destroy(h);
+    return s;
+  };
+  if (hipGetDevice(&h->device) != hipSuccess) return bail(fail(h, NNP_E_HIP, "hipGetDevice failed"));
+  if (prec == NNP_FP64) {
+    if (hipMalloc(&h->d_tab, sizeof(DevTab<double>)) != hipSuccess) return bail(fail(h, NNP_E_NOMEM, "table alloc"));
+    if (hipMemcpy(h->d_tab, &h->tab_d, sizeof(DevTab<double>), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(h, NNP_E_HIP, "table upload failed"));
+  } else {
+    DevTab<float> tf = convert_tab<float>(h->tab_d);
+    if (hipMalloc(&h->d_tab, sizeof(DevTab<float>)) != hipSuccess) return bail(fail(h, NNP_E_NOMEM, "table alloc"));
+    if (hipMemcpy(h->d_tab, &tf, sizeof(DevTab<float>), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(h, NNP_E_HIP, "table upload failed"));
+  }
+  if (hipMalloc(&h->d_flatmap, h->flatmap.size() * sizeof(int)) != hipSuccess)
+    return bail(fail(h, NNP_E_NOMEM, "flatmap alloc"));
+  if (hipMemcpy(h->d_flatmap, h->flatmap.data(), h->flatmap.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(h, NNP_E_HIP, "flatmap upload"));
+  if ((st = upload_params(h))) return bail(st);
+  if (hipHostMalloc((void**)&h->h_flags, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return bail(fail(h, NNP_E_NOMEM, "pinned flags"));
+  if (hipHostMalloc((void**)&h->h_energy, sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return bail(fail(h, NNP_E_NOMEM, "pinned energy"));
+  *out = h;
+  return NNP_OK;
+}
+
+nnp_status nnp_compute_batch(nnp_handle* h, int n_struct, const int64_t* atom_offsets, const void* pos,
+                             const int32_t* types, const double* boxes, double* energies, void* atom_energy,
+                             void* forces, void* stream) {
+  if (!h) return NNP_E_ARG;
+  h->err.clear();
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  switch (h->prec) {
+    case NNP_FP64: return forward<P_FP64>(h, n_struct, atom_offsets, pos, types, boxes, energies, nullptr, atom_energy, forces, s);
+    case NNP_FP32: return forward<P_FP32>(h, n_struct, atom_offsets, pos, types, boxes, energies, nullptr, atom_energy, forces, s);
+    default: return forward<P_BF16>(h, n_struct, atom_offsets, pos, types, boxes, energies, nullptr, atom_energy, forces, s);
+  }
+}
+
+nnp_status nnp_compute(nnp_handle* h, int64_t n_atoms, const void* pos, const int32_t* types, const double box[3],
+                       double* energy, void* atom_energy, void* forces, void* stream) {
+  if (!h) return NNP_E_ARG;
+  h->err.clear();
+  if (n_atoms < 0) return fail(h, NNP_E_ARG, "n_atoms must be >= 0");
+  if (!box) return fail(h, NNP_E_ARG, "box must not be NULL");
+  const int64_t offs[2] = {0, n_atoms};
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  double e = 0.0;
+  nnp_status st;
+  switch (h->prec) {
+    case NNP_FP64: st = forward<P_FP64>(h, 1, offs, pos, types, box, nullptr, &e, atom_energy, forces, s); break;
+    case NNP_FP32: st = forward<P_FP32>(h, 1, offs, pos, types, box, nullptr, &e, atom_energy, forces, s); break;
+    default: st = forward<P_BF16>(h, 1, offs, pos, types, box, nullptr, &e, atom_energy, forces, s); break;
+  }
+  if (st == NNP_OK && energy) *energy = e;
+  return st;
+}
+
+nnp_status nnp_backward(nnp_handle* h, int n_struct, const int64_t* atom_offsets, const void* pos,
+                        const int32_t* types, const double* boxes, const double* dL_dE, const void* dL_dF,
+                        void* grad_params, void* stream) {
+  if (!h) return NNP_E_ARG;
+  h->err.clear();
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  switch (h->prec) {
+    case NNP_FP64: return backward<P_FP64>(h, n_struct, atom_offsets, pos, types, boxes, dL_dE, dL_dF, (double*)grad_params, s);
+    case NNP_FP32: return backward<P_FP32>(h, n_struct, atom_offsets, pos, types, boxes, dL_dE, dL_dF, (double*)grad_params, s);
+    default: return fail(h, NNP_E_STATE, "nnp_backward needs an NNP_FP64 or NNP_FP32 handle");
+  }
+}
+
+int64_t nnp_n_params(const nnp_handle* h) { return h ? (int64_t)h->params.size() : 0; }
+
+nnp_status nnp_set_params(nnp_handle* h, const void* flat, int on_device) {
+  if (!h) return NNP_E_ARG;
+  h->err.clear();
+  if (!flat) return fail(h, NNP_E_ARG, "flat_params must not be NULL");
+  std::vector<double> p(h->params.size());
+  if (on_device) {
+    NNP_HIP(h, hipDeviceSynchronize());
+    NNP_HIP(h, hipMemcpy(p.data(), flat, p.size() * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(p.data(), flat, p.size() * sizeof(double));
+  }
+  for (double v : p)
+    if (!std::isfinite(v)) return fail(h, NNP_E_ARG, "non-finite parameter");
+  h->params = p;
+  return upload_params(h);
+}
+
+nnp_status nnp_get_params(const nnp_handle* h, double* out) {
+  if (!h || !out) return NNP_E_ARG;
+  std::memcpy(out, h->params.data(), h->params.size() * sizeof(double));
+  return NNP_OK;
+}
+
+nnp_status nnp_set_profiling(nnp_handle* h, int enable) {
+  if (!h) return NNP_E_ARG;
+  h->prof = enable != 0;
+  return NNP_OK;
+}
+
+int nnp_last_timings(const nnp_handle* h, const char** names, double* ms, int max_k) {
+  if (!h) return 0;
+  const int k = std::min<int>(max_k, (int)h->t_ms.size());
+  for (int i = 0; i < k; ++i) {
+    if (names) names[i] = h->t_names[i];
+    if (ms) ms[i] = h->t_ms[i];
+  }
+  return k;
+}
+
+int nnp_neighbor_capacity(const nnp_handle* h) { return h ? h->cap : 0; }
+
+nnp_status nnp_set_neighbor_capacity(nnp_handle* h, int cap) {
+  if (!h) return NNP_E_ARG;
+  if (cap < 8) return fail(h, NNP_E_ARG, "capacity must be >= 8");
+  h->cap_override = cap;
+  h->cap = cap;
+  return NNP_OK;
+}
+
+void nnp_destroy(nnp_handle* h) {
+  if (!h) return;
+  for (auto& kv : h->ws)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  if (h->d_tab) (void)hipFree(h->d_tab);
+  if (h->d_nets) (void)hipFree(h->d_nets);
+  if (h->d_flatmap) (void)hipFree(h->d_flatmap);
+  if (h->h_stage) (void)hipHostFree(h->h_stage);
+  if (h->h_flags) (void)hipHostFree(h->h_flags);
+  if (h->h_energy) (void)hipHostFree(h->h_energy);
+  for (auto e : h->events) (void)hipEventDestroy(e);
+  delete h;
+}
+
+const char* nnp_last_error(const nnp_handle* h) { return h ? h->err.c_str() : nnp::g_create_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,172 @@
+// Shared definitions of the gfx950 kernels and the host layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nnp {
+
+// ------------------------------------------------------------------ limits
+constexpr int MAX_EL = 4;                            // elements
+constexpr int MAX_CLS = MAX_EL * (MAX_EL + 1) / 2;   // unordered neighbour-element pairs
+constexpr int MAX_SF = 32;                           // SFs per centre element (network inputs)
+constexpr int MAX_RAD = 16;                          // radial SFs per (centre, neighbour element)
+constexpr int MAX_ANG = 8;                           // angular SFs per (centre, neighbour pair)
+constexpr int MAX_NE = 4;                            // distinct angular eta per centre element
+constexpr int HID = 32;                              // padded hidden width and input width
+constexpr int LD = 32;                               // row stride of G, dE/dG and JVP rows
+constexpr int FC_DEG_MAX = 16;                       // storage bound of the cutoff polynomial
+constexpr int WAVE = 64;
+constexpr int QCAP = 128;                            // per-wave triplet queue (ring)
+
+enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2 };
+
+// Arithmetic types of each form.
+//  T     symmetry-function and geometry arithmetic
+//  Acc   per-atom SF neighbour sums
+//  FAcc  force accumulation
+//  IO    positions, per-atom energies and forces at the boundary; G~ and dE/dG rows
+template <int P> struct Types;
+template <> struct Types<P_FP64> { using T = double; using Acc = double; using FAcc = double; using IO = double; };
+template <> struct Types<P_FP32> { using T = float;  using Acc = float;  using FAcc = float;  using IO = float; };
+template <> struct Types<P_BF16> { using T = float;  using Acc = double; using FAcc = double; using IO = float; };
+
+// -------------------------------------------------------------- SF table
+// Device copy of the symmetry-function table, in the arithmetic type T.
+// Every field is read with wave-uniform (scalar) loads.
+template <class T>
+struct DevTab {
+  int n_el;
+  int n_sf[MAX_EL];
+  T rc2;                               // rc^2
+  // fc(r) = sum_n fc_c[n] s^n with s = r^2 for r < rc (Taylor series of
+  // (1 + cos(pi sqrt(s)/rc))/2 in s), and dfc/ds = sum_n fc_d[n] s^n.
+  T fc_c[FC_DEG_MAX + 1];
+  T fc_d[FC_DEG_MAX + 1];
+  // radial SFs, per (centre e, neighbour element f)
+  int rad_cnt[MAX_EL][MAX_EL];
+  T rad_eta[MAX_EL][MAX_EL][MAX_RAD];
+  T rad_rs[MAX_EL][MAX_EL][MAX_RAD];
+  int rad_out[MAX_EL][MAX_EL][MAX_RAD];
+  // distinct angular exponents per centre element
+  int n_eta[MAX_EL];
+  T aeta[MAX_EL][MAX_NE];              // eta
+  T aeta2[MAX_EL][MAX_NE];             // eta * log2(e)
+  // angular SFs, per (centre e, neighbour-pair class c)
+  int ang_cnt[MAX_EL][MAX_CLS];
+  int ang_eta[MAX_EL][MAX_CLS][MAX_ANG];   // index into aeta[e]
+  int ang_zeta[MAX_EL][MAX_CLS][MAX_ANG];
+  int ang_lam[MAX_EL][MAX_CLS][MAX_ANG];   // +1 / -1
+  T ang_pre[MAX_EL][MAX_CLS][MAX_ANG];     // 2^(1 - zeta)
+  int ang_out[MAX_EL][MAX_CLS][MAX_ANG];
+  // centring / scaling of the network inputs (applied in FP64 to the sums)
+  double shift_d[MAX_EL][MAX_SF];
+  double inv_scale_d[MAX_EL][MAX_SF];
+};
+
+// Per-structure geometry of a batch.
+struct DevStruct {
+  double L[3];
+  double invL[3];
+  int ncell[3];
+  int cellbase;     // first cell id of this structure in the batch-wide cell numbering
+  int64_t off;      // first atom (caller order)
+  int64_t n;        // atoms
+};
+
+// Network parameters of one element, zero-padded to HID x HID (T = math type).
+// Layout: W1[HID][HID] (out, in), b1[HID], W2[HID][HID], b2[HID], w3[HID], b3 (+ pad).
+constexpr int NET_STRIDE = 2 * HID * HID + 4 * HID;
+constexpr int OFF_W1 = 0, OFF_B1 = HID * HID, OFF_W2 = HID * HID + HID, OFF_B2 = 2 * HID * HID + HID,
+              OFF_W3 = 2 * HID * HID + 2 * HID, OFF_B3 = 2 * HID * HID + 3 * HID;
+
+// Packed element / structure id stored in the 4th lane of the sorted positions.
+__host__ __device__ inline long long pack_ids(int elem, int strct) { return (long long)elem | ((long long)strct << 8); }
+__device__ inline int elem_of(double w) { return (int)(__double_as_longlong(w) & 0xff); }
+__device__ inline int struct_of(double w) { return (int)(__double_as_longlong(w) >> 8); }
+
+// Neighbour-pair class index of elements e1 <= e2 among n_el elements.
+__host__ __device__ inline int class_index(int e1, int e2, int n_el) { return e1 * n_el - e1 * (e1 - 1) / 2 + (e2 - e1); }
+
+// ----------------------------------------------------------- wave helpers
+template <class T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+__device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Number of set bits of mask below this lane.
+__device__ inline int lanes_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// exp(x) in the arithmetic type: FP64 through the device math library, FP32
+// through the hardware base-2 exponential of x log2(e) (the caller passes
+// the argument already multiplied by log2(e)).
+__device__ inline double exp_scaled(double x_ln, double /*x_log2*/) { return exp(x_ln); }
+__device__ inline float exp_scaled(float /*x_ln*/, float x_log2) { return __builtin_amdgcn_exp2f(x_log2); }
+
+__device__ inline double rsqrt_t(double s) { return 1.0 / sqrt(s); }
+__device__ inline float rsqrt_t(float s) { return __builtin_amdgcn_rsqf(s); }
+
+// Degree of the cutoff polynomial per arithmetic type: the first omitted
+// Taylor term is below 2e-9 (FP32, degree 9) or 2e-18 (FP64, degree 14) on
+// [0, rc^2].
+template <class T> struct FcDeg;
+template <> struct FcDeg<float> { static constexpr int v = 9; };
+template <> struct FcDeg<double> { static constexpr int v = 14; };
+
+// Cutoff coefficients held in registers for the lifetime of a kernel.
+template <class T>
+struct Cutoff {
+  static constexpr int D = FcDeg<T>::v;
+  T c[D + 1], d[D];
+  T rc2;
+  __device__ inline void load(const DevTab<T>* tab) {
+#pragma unroll
+    for (int n = 0; n <= D; ++n) c[n] = tab->fc_c[n];
+#pragma unroll
+    for (int n = 0; n < D; ++n) d[n] = tab->fc_d[n];
+    rc2 = tab->rc2;
+  }
+  // fc and dfc/ds at s = r^2 (Horner); exactly 0 for s >= rc^2.
+  __device__ inline void eval(T s, T& fc, T& dfc_ds) const {
+    T f = c[D], g = d[D - 1];
+#pragma unroll
+    for (int n = D - 1; n >= 0; --n) f = f * s + c[n];
+#pragma unroll
+    for (int n = D - 2; n >= 0; --n) g = g * s + d[n];
+    const bool in = s < rc2;
+    fc = in ? f : T(0);
+    dfc_ds = in ? g : T(0);
+  }
+  __device__ inline T value(T s) const {
+    T f = c[D];
+#pragma unroll
+    for (int n = D - 1; n >= 0; --n) f = f * s + c[n];
+    return s < rc2 ? f : T(0);
+  }
+};
+
+// x^n for a wave-uniform integer n >= 0 (binary powering; 0^0 = 1).
+template <class T>
+__device__ inline T ipow(T x, int n) {
+  T r = T(1);
+  while (n) {
+    if (n & 1) r *= x;
+    x *= x;
+    n >>= 1;
+  }
+  return r;
+}
+
+// Atomic add without return value (hardware float/double atomics).
+__device__ inline void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
+__device__ inline void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+}  // namespace nnp

@@ -1,0 +1,255 @@
+// Per-element atomic networks (Sec. 3.1 step 2, Fig. 1(c)) and their
+// derivatives:
+//   forward   h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), E_i = w3 . h2 + b3
+//             on the scaled descriptors x = G~;
+//   dE/dG     c = diag(1/scale) W1^T [(1 - h1^2) o W2^T [(1 - h2^2) o w3]]
+//             (the network part of step 3, counted with the forces in the
+//             paper's Fig. 5);
+//   weights   differentiation form: gradient of sum_i [a_i E_i - <dE_i/dx_i, t_i>]
+//             with a tangent t_i per atom (forward-over-reverse).
+// Sorted atoms of one element are contiguous, so every workgroup works on
+// rows of a single element and reads that element's weights with uniform
+// loads.
+#include "kernels.h"
+
+namespace nnp {
+
+// Workgroup b -> (element, first row) for tiles of `rows` rows per element.
+__device__ inline bool element_tile(int b, int rows, int n_el, const int* __restrict__ eoff, int& e, int64_t& r0,
+                                    int64_t& r1) {
+  int acc = 0;
+  for (int f = 0; f < n_el; ++f) {
+    const int64_t lo = eoff[f], hi = eoff[f + 1];
+    const int nt = (int)((hi - lo + rows - 1) / rows);
+    if (b < acc + nt) {
+      e = f;
+      r0 = lo + (int64_t)(b - acc) * rows;
+      r1 = hi;
+      return true;
+    }
+    acc += nt;
+  }
+  return false;
+}
+
+__device__ inline float tanh_t(float x) { return tanhf(x); }
+__device__ inline double tanh_t(double x) { return tanh(x); }
+
+// One thread per atom, VALU FMAs (forward + input gradient).
+template <int P>
+__global__ void __launch_bounds__(256) k_mlp_valu(MlpArgs<P> a) {
+  using T = typename Types<P>::T;
+  using IO = typename Types<P>::IO;
+  int e;
+  int64_t r0, r1;
+  if (!element_tile(blockIdx.x, 256, a.n_el, a.eoff, e, r0, r1)) return;
+  e = uniform(e);
+  const int64_t r = r0 + threadIdx.x;
+  if (r >= r1) return;
+  const T* __restrict__ W = a.nets + (size_t)e * NET_STRIDE;
+  T x[HID], h1[HID], h2[HID];
+#pragma unroll
+  for (int k = 0; k < HID; ++k) x[k] = (T)a.G[r * LD + k];
+#pragma unroll
+  for (int o = 0; o < HID; ++o) {
+    T z = W[OFF_B1 + o];
+#pragma unroll
+    for (int k = 0; k < HID; ++k) z += W[OFF_W1 + o * HID + k] * x[k];
+    h1[o] = tanh_t(z);
+  }
+#pragma unroll
+  for (int o = 0; o < HID; ++o) {
+    T z = W[OFF_B2 + o];
+#pragma unroll
+    for (int k = 0; k < HID; ++k) z += W[OFF_W2 + o * HID + k] * h1[k];
+    h2[o] = tanh_t(z);
+  }
+  T E = W[OFF_B3];
+#pragma unroll
+  for (int o = 0; o < HID; ++o) E += W[OFF_W3 + o] * h2[o];
+  a.Ei[r] = (IO)E;
+  // backward: d2 = w3 (1 - h2^2) (in h2), d1 = (1 - h1^2) W2^T d2 (in h1)
+#pragma unroll
+  for (int o = 0; o < HID; ++o) h2[o] = W[OFF_W3 + o] * (T(1) - h2[o] * h2[o]);
+#pragma unroll
+  for (int k = 0; k < HID; ++k) {
+    T s = T(0);
+#pragma unroll
+    for (int o = 0; o < HID; ++o) s += W[OFF_W2 + o * HID + k] * h2[o];
+    x[k] = s * (T(1) - h1[k] * h1[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < HID; ++k) {
+    T s = T(0);
+#pragma unroll
+    for (int o = 0; o < HID; ++o) s += W[OFF_W1 + o * HID + k] * x[o];
+    const T isc = k < MAX_SF ? (T)a.tab->inv_scale_d[e][k] : T(0);
+    a.C[r * LD + k] = (IO)(s * isc);
+  }
+}
+
+template <int P>
+void launch_mlp(const MlpArgs<P>& a, hipStream_t stream) {
+  if (a.n == 0) return;
+  const unsigned g = (unsigned)((a.n + 255) / 256 + a.n_el);
+  hipLaunchKernelGGL(k_mlp_valu<P>, dim3(g), dim3(256), 0, stream, a);
+}
+
+// ------------------------------------------------------------ weight gradient
+// Per-atom vectors of the forward-over-reverse pass, stored for the
+// parameter reduction:  [x, t, h1, dh1, zb1, dzb1, h2, dh2, zb2, dzb2, alpha]
+// where t is the tangent (JVP row / scale), dh = tangent of h, zb/dzb the
+// adjoints of the pre-activations of the primal and tangent chains.
+constexpr int WG_VEC = 11;
+
+template <int P>
+__global__ void __launch_bounds__(256) k_wgrad_atoms(WGradArgs<P> a) {
+  using T = typename Types<P>::T;
+  int e;
+  int64_t r0, r1;
+  if (!element_tile(blockIdx.x, 256, a.n_el, a.eoff, e, r0, r1)) return;
+  e = uniform(e);
+  const int64_t r = r0 + threadIdx.x;
+  if (r >= r1) return;
+  const T* __restrict__ W = a.nets + (size_t)e * NET_STRIDE;
+  T* out = a.vec + r * (WG_VEC * HID);
+  T x[HID], t[HID], h1[HID], dz1[HID];
+#pragma unroll
+  for (int k = 0; k < HID; ++k) {
+    x[k] = (T)a.G[r * LD + k];
+    t[k] = (T)a.V[r * LD + k] * (k < MAX_SF ? (T)a.tab->inv_scale_d[e][k] : T(0));
+  }
+#pragma unroll
+  for (int o = 0; o < HID; ++o) {
+    T z = W[OFF_B1 + o], dz = T(0);
+#pragma unroll
+    for (int k = 0; k < HID; ++k) {
+      z += W[OFF_W1 + o * HID + k] * x[k];
+      dz += W[OFF_W1 + o * HID + k] * t[k];
+    }
+    h1[o] = tanh_t(z);
+    dz1[o] = dz;
+    out[0 * HID + o] = x[o];
+    out[1 * HID + o] = t[o];
+    out[2 * HID + o] = h1[o];
+    out[3 * HID + o] = (T(1) - h1[o] * h1[o]) * dz;
+  }
+  const T alpha = a.gE_atom ? (T)a.gE_atom[r] : T(0);
+  // Objective J = alpha E - w3 . dh2, dh2 = (1 - h2^2) dz2.
+  T zb2[HID], dzb2[HID];
+#pragma unroll
+  for (int o = 0; o < HID; ++o) {
+    T z = W[OFF_B2 + o], dz = T(0);
+#pragma unroll
+    for (int k = 0; k < HID; ++k) {
+      const T w = W[OFF_W2 + o * HID + k];
+      z += w * h1[k];
+      dz += w * ((T(1) - h1[k] * h1[k]) * dz1[k]);
+    }
+    const T h2 = tanh_t(z);
+    const T g2 = T(1) - h2 * h2;
+    const T w3 = W[OFF_W3 + o];
+    // adjoint of h2: alpha w3 from E, and from -w3 . (1 - h2^2) dz2: +2 w3 h2 dz2
+    const T h2bar = alpha * w3 + T(2) * w3 * h2 * dz;
+    zb2[o] = g2 * h2bar;
+    dzb2[o] = -g2 * w3;
+    out[6 * HID + o] = h2;
+    out[7 * HID + o] = g2 * dz;
+    out[8 * HID + o] = zb2[o];
+    out[9 * HID + o] = dzb2[o];
+  }
+#pragma unroll
+  for (int k = 0; k < HID; ++k) {
+    T hb = T(0), dhb = T(0);
+#pragma unroll
+    for (int o = 0; o < HID; ++o) {
+      hb += W[OFF_W2 + o * HID + k] * zb2[o];
+      dhb += W[OFF_W2 + o * HID + k] * dzb2[o];
+    }
+    const T g1 = T(1) - h1[k] * h1[k];
+    // dh1 = (1 - h1^2) dz1 contributes -2 h1 dz1 dhb to the adjoint of h1
+    hb += dhb * (T(-2) * h1[k] * dz1[k]);
+    out[4 * HID + k] = g1 * hb;
+    out[5 * HID + k] = g1 * dhb;
+  }
+  out[10 * HID] = alpha;
+}
+
+// partial[(e * nch + ch) * NET_STRIDE + p]: sum over one chunk of atoms of
+// element e of the per-atom gradient of parameter p (padded layout).
+template <class T>
+__global__ void __launch_bounds__(256) k_wgrad_chunks(const int* __restrict__ eoff, int chunk, int nch,
+                                                      const T* __restrict__ vec, double* __restrict__ partial) {
+  const int e = blockIdx.z;
+  const int ch = blockIdx.y;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= NET_STRIDE) return;
+  const int64_t lo = eoff[e] + (int64_t)ch * chunk;
+  const int64_t hi = min((int64_t)eoff[e + 1], lo + chunk);
+  double s = 0.0;
+  for (int64_t r = lo; r < hi; ++r) {
+    const T* v = vec + r * (WG_VEC * HID);
+    T g;
+    if (p < OFF_B1) {  // W1[o][k]: zb1[o] x[k] + dzb1[o] t[k]
+      const int o = p / HID, k = p % HID;
+      g = v[4 * HID + o] * v[0 * HID + k] + v[5 * HID + o] * v[1 * HID + k];
+    } else if (p < OFF_W2) {
+      g = v[4 * HID + (p - OFF_B1)];
+    } else if (p < OFF_B2) {  // W2[o][k]: zb2[o] h1[k] + dzb2[o] dh1[k]
+      const int q = p - OFF_W2, o = q / HID, k = q % HID;
+      g = v[8 * HID + o] * v[2 * HID + k] + v[9 * HID + o] * v[3 * HID + k];
+    } else if (p < OFF_W3) {
+      g = v[8 * HID + (p - OFF_B2)];
+    } else if (p < OFF_B3) {  // w3[o]: alpha h2[o] - dh2[o]
+      const int o = p - OFF_W3;
+      g = v[10 * HID] * v[6 * HID + o] - v[7 * HID + o];
+    } else if (p == OFF_B3) {
+      g = v[10 * HID];
+    } else {
+      g = T(0);
+    }
+    s += (double)g;
+  }
+  partial[((size_t)e * nch + ch) * NET_STRIDE + p] = s;
+}
+
+// out[e][p] = sum over the chunks of element e in chunk order (FP64).
+__global__ void __launch_bounds__(256) k_wgrad_final(int nch, const double* __restrict__ partial,
+                                                     double* __restrict__ out) {
+  const int e = blockIdx.y;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= NET_STRIDE) return;
+  double s = 0.0;
+  for (int ch = 0; ch < nch; ++ch) s += partial[((size_t)e * nch + ch) * NET_STRIDE + p];
+  out[(size_t)e * NET_STRIDE + p] = s;
+}
+
+// Padded gradient -> caller's flat parameter layout.
+__global__ void __launch_bounds__(256) k_unpad(int64_t np, const int* __restrict__ map, const double* __restrict__ padded,
+                                               double* __restrict__ flat) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < np) flat[i] = padded[map[i]];
+}
+
+template <int P>
+void launch_wgrad(const WGradArgs<P>& a, hipStream_t stream) {
+  using T = typename Types<P>::T;
+  const unsigned gx = (NET_STRIDE + 255) / 256;
+  if (a.n > 0) {
+    const unsigned g = (unsigned)((a.n + 255) / 256 + a.n_el);
+    hipLaunchKernelGGL(k_wgrad_atoms<P>, dim3(g), dim3(256), 0, stream, a);
+  }
+  hipLaunchKernelGGL(k_wgrad_chunks<T>, dim3(gx, a.nch, a.n_el), dim3(256), 0, stream, a.eoff, a.chunk, a.nch,
+                     (const T*)a.vec, a.partial);
+  hipLaunchKernelGGL(k_wgrad_final, dim3(gx, a.n_el), dim3(256), 0, stream, a.nch, a.partial, a.padded);
+  hipLaunchKernelGGL(k_unpad, dim3((unsigned)((a.n_params + 255) / 256)), dim3(256), 0, stream, a.n_params, a.flatmap,
+                     a.padded, a.out);
+}
+
+template void launch_mlp<P_FP64>(const MlpArgs<P_FP64>&, hipStream_t);
+template void launch_mlp<P_FP32>(const MlpArgs<P_FP32>&, hipStream_t);
+template void launch_mlp<P_BF16>(const MlpArgs<P_BF16>&, hipStream_t);
+template void launch_wgrad<P_FP64>(const WGradArgs<P_FP64>&, hipStream_t);
+template void launch_wgrad<P_FP32>(const WGradArgs<P_FP32>&, hipStream_t);
+
+}  // namespace nnp

@@ -1,0 +1,8 @@
+// Instantiation of the pair/triplet kernels for one arithmetic form.
+#include "kernels.h"
+#include "k_triplet.inc"
+
+namespace nnp {
+template void launch_triplet<P_FP64>(int, int, const TripArgs<P_FP64>&, hipStream_t);
+template size_t triplet_lds_bytes<P_FP64>(int, int, int);
+}  // namespace nnp

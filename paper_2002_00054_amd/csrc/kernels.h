@@ -1,0 +1,114 @@
+// Launch interfaces of the gfx950 kernels (host side).
+#pragma once
+
+#include "common.h"
+
+namespace nnp {
+
+// ---------------------------------------------------------------- K1/K2
+struct BinArgs {
+  int64_t n;                 // atoms of the batch
+  const int32_t* types;      // caller order
+  const DevStruct* st;       // [n_struct]
+  const int64_t* soff;       // [n_struct + 1] atom offsets (device)
+  int n_struct;
+  int n_el;
+  int total_cells;           // cells of all structures
+  int* key;                  // [n]
+  int* count;                // [n_el * total_cells + 1]
+  int* start;                // [n_el * total_cells + 1]
+  int* cursor;               // [n_el * total_cells + 1]
+  int* perm;                 // [n] sorted -> caller index
+  double4* pos4;             // [n] sorted wrapped positions + ids
+  int* eoff;                 // [n_el + 1] element offsets of the sorted order
+  int* flags;                // [0] bad type, [1] max neighbour count beyond cap
+};
+
+void launch_fill_int(int* p, int64_t n, int v, hipStream_t stream);
+template <class TIn>
+void launch_bin_sort(const BinArgs& a, const TIn* pos, hipStream_t stream);
+void launch_neighbors(const BinArgs& a, double rc, int cap, int* nbr, int4* nnb, hipStream_t stream);
+
+// ---------------------------------------------------------------- K3/K5/K7
+template <int P>
+struct TripArgs {
+  using T = typename Types<P>::T;
+  using IO = typename Types<P>::IO;
+  using FAcc = typename Types<P>::FAcc;
+  int64_t n;                 // sorted atoms
+  int cap;                   // neighbour slots per atom
+  const double4* pos4;
+  const int* nbr;            // [n][cap]
+  const int4* nnb;           // [n] neighbours per element block
+  const DevStruct* st;
+  const DevTab<T>* tab;
+  IO* G;                     // SF: G~ rows [n][LD]
+  const IO* C;               // FORCE: dE/dG rows [n][LD]
+  FAcc* F;                   // FORCE: force accumulator [n][3] (sorted)
+  const IO* delta;           // JVP: dL/dF [n][3] (sorted)
+  IO* V;                     // JVP: rows [n][LD]
+};
+
+template <int P>
+void launch_triplet(int mode, int ne, const TripArgs<P>& a, hipStream_t stream);
+template <int P>
+size_t triplet_lds_bytes(int mode, int ne, int cap);
+
+// ---------------------------------------------------------------- K4/K8
+template <int P>
+struct MlpArgs {
+  using T = typename Types<P>::T;
+  using IO = typename Types<P>::IO;
+  int64_t n;                 // sorted atoms
+  int n_el;
+  const int* eoff;           // [n_el + 1] (device)
+  const IO* G;               // [n][LD] scaled inputs
+  IO* C;                     // [n][LD] dE/dG (raw G)
+  IO* Ei;                    // [n] atomic energies (sorted)
+  const T* nets;             // [n_el][NET_STRIDE] padded parameters
+  const uint16_t* bf;        // BF16 form: split weights (see k_mlp.hip), else null
+  const DevTab<T>* tab;
+};
+template <int P>
+void launch_mlp(const MlpArgs<P>& a, hipStream_t stream);
+
+// Weight gradient of sum_i [a_i E_i - <dE_i/dG~_i, t_i>] with t = V / scale
+// (differentiation form), reduced over atoms in FP64 chunks.
+template <int P>
+struct WGradArgs {
+  using T = typename Types<P>::T;
+  using IO = typename Types<P>::IO;
+  int64_t n;
+  int n_el;
+  const int* eoff;
+  const IO* G;               // [n][LD] scaled inputs
+  const IO* V;               // [n][LD] JVP rows (raw G)
+  const double* gE_atom;     // [n] dL/dE of each atom's structure (sorted), or null
+  const T* nets;
+  const DevTab<T>* tab;
+  T* vec;                    // [n][11 * HID] per-atom vectors
+  int chunk, nch;            // atoms per partial, partials per element (>= ceil(max N_e / chunk))
+  double* partial;           // [n_el][nch][NET_STRIDE]
+  double* padded;            // [n_el][NET_STRIDE]
+  int64_t n_params;
+  const int* flatmap;        // [n_params] flat index -> padded index
+  double* out;               // [n_params] caller layout
+};
+template <int P>
+void launch_wgrad(const WGradArgs<P>& a, hipStream_t stream);
+
+// ---------------------------------------------------------------- K6 + misc
+template <class T>
+void launch_fill(T* p, int64_t n, T v, hipStream_t stream);
+template <class IO, class FAcc>
+void launch_unpermute(int64_t n, const int* perm, const IO* Ei_s, const FAcc* F_s, double* Ei_o, IO* Ei_out,
+                      IO* F_out, hipStream_t stream);
+template <class IO>
+void launch_permute_rows3(int64_t n, const int* perm, const IO* in, IO* out, hipStream_t stream);
+void launch_gather_struct_grad(int64_t n, const int* perm, const int64_t* soff, int n_struct, const double* gE,
+                               double* gE_atom, hipStream_t stream);
+// Deterministic energy sums: chunk partials then per-structure sums.
+void launch_energy(const double* Ei_o, const int64_t* chunk_lo, const int64_t* chunk_hi, int nchunk,
+                   const int* struct_chunk, int n_struct, double* partial, double* energies, hipStream_t stream);
+
+}  // namespace nnp

@@ -1,0 +1,166 @@
+"""GPU path (through the C ABI) against the FP64 oracle, element by element.
+
+Tolerances: FP64 form 1e-9 relative (per-atom energy against max(|E_i|,
+rms E), forces against rms F); FP32 form 1e-5 eV per atom and 1e-4 eV/A per
+force component.  The FP32 forms see float32 positions, and so does the
+oracle they are compared with.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from common import oracle_water, water_potential
+from gpu_common import check_fp32, check_fp64, make_potential, oracle_input, run, say, to_dev
+from paper_2002_00054_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pots():
+    return {p: make_potential(p) for p in ("fp64", "fp32")}
+
+
+@pytest.fixture(scope="module")
+def opot():
+    return oracle_water()
+
+
+def _ref(opot, b, precision, use_cells=False):
+    out = opot.compute(oracle_input(b, precision), b.types, b.box, use_cells=use_cells)
+    return out["E"], out["Ei"], out["F"]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_fp64_config0(pots, opot, seed):
+    b = synth.water_box(4, seed)
+    say("fp64 192 atoms seed", seed)
+    e, ei, f = run(pots["fp64"], b)
+    E, Ei, F = _ref(opot, b, "fp64")
+    check_fp64(ei, f, Ei, F)
+    assert abs(e - E) <= 1e-9 * abs(E) + 1e-9
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_fp32_config0(pots, opot, seed):
+    b = synth.water_box(4, seed)
+    say("fp32 192 atoms seed", seed)
+    e, ei, f = run(pots["fp32"], b)
+    E, Ei, F = _ref(opot, b, "fp32")
+    check_fp32(ei, f, Ei, F)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_config1(pots, opot, precision):
+    b = synth.water_box(16, 11)
+    say(precision, "12288 atoms seed 11")
+    e, ei, f = run(pots[precision], b)
+    E, Ei, F = _ref(opot, b, precision, use_cells=True)
+    if precision == "fp64":
+        check_fp64(ei, f, Ei, F)
+    else:
+        check_fp32(ei, f, Ei, F)
+    assert abs(e - E) <= 1e-9 * b.n_atoms * (1 if precision == "fp64" else 1e4)
+
+
+def test_ragged_sizes_and_shapes(pots, opot):
+    """Non-cubic boxes, axes with 1, 2 and many cells, and atom counts that
+    leave ragged tiles (not multiples of 4 waves / 256 threads)."""
+    rng = np.random.default_rng(5)
+    for L, n_atoms in (((12.5, 19.0, 31.0), 250), ((13.0, 13.0, 13.0), 7), ((40.0, 12.1, 12.1), 333)):
+        L = np.array(L)
+        pos = rng.uniform(0, 1, size=(n_atoms, 3)) * L
+        # keep atoms >= 0.9 A apart so the configuration is physical
+        keep = [0]
+        for i in range(1, n_atoms):
+            d = pos[keep] - pos[i]
+            d -= L * np.round(d / L)
+            if np.min(np.linalg.norm(d, axis=1)) > 0.9:
+                keep.append(i)
+        pos = pos[keep]
+        types = rng.integers(0, 2, size=len(pos)).astype(np.int32)
+        b = synth.Box(pos=pos, types=types, box=L)
+        say("ragged box", L, len(pos))
+        e, ei, f = run(pots["fp64"], b)
+        E, Ei, F = _ref(opot, b, "fp64")
+        check_fp64(ei, f, Ei, F)
+
+
+def test_positions_outside_box_are_wrapped(pots, opot):
+    b = synth.water_box(4, 2)
+    shifted = synth.Box(pos=b.pos + b.box * np.array([3.0, -2.0, 1.0]), types=b.types, box=b.box)
+    e0, ei0, f0 = run(pots["fp64"], b)
+    e1, ei1, f1 = run(pots["fp64"], shifted)
+    check_fp64(ei1, f1, ei0, f0, rel=1e-11)
+
+
+def test_empty_and_isolated(pots):
+    import torch
+
+    pot = pots["fp64"]
+    pos = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    types = torch.zeros(0, dtype=torch.int32, device="cuda")
+    e, ei, f = pot.compute(pos, types, (20.0, 20.0, 20.0))
+    assert e == 0.0 and ei.numel() == 0
+    # one atom: no neighbours, G = 0, E = NN(-shift/scale), F = 0
+    b = synth.Box(pos=np.array([[1.0, 2.0, 3.0]]), types=np.array([1], dtype=np.int32), box=np.array([20.0] * 3))
+    e, ei, f = run(pot, b)
+    out = oracle_water().compute(b.pos, b.types, b.box)
+    assert ei[0] == pytest.approx(out["Ei"][0], rel=1e-12)
+    assert np.all(f == 0.0)
+
+
+def test_neighbor_capacity_regrow(opot):
+    pot = make_potential("fp64")
+    pot.set_neighbor_capacity(8)
+    b = synth.water_box(4, 3)
+    e, ei, f = run(pot, b)
+    assert pot.neighbor_capacity > 90
+    E, Ei, F = _ref(opot, b, "fp64")
+    check_fp64(ei, f, Ei, F)
+
+
+def test_errors_are_reported(pots):
+    import torch
+
+    from paper_2002_00054_amd.nnp import NNPError
+
+    pot = pots["fp64"]
+    b = synth.water_box(4, 1)
+    pos, types = to_dev(b, torch.float64)
+    with pytest.raises(NNPError, match="NNP_E_BOX"):
+        pot.compute(pos, types, (11.0, 12.42, 12.42))
+    bad = types.clone()
+    bad[5] = 7
+    with pytest.raises(NNPError, match="NNP_E_TYPE"):
+        pot.compute(pos, bad, b.box)
+    bad[5] = -1
+    with pytest.raises(NNPError, match="NNP_E_TYPE"):
+        pot.compute(pos, bad, b.box)
+    # the handle still works afterwards
+    e, ei, f = run(pot, b)
+    assert np.isfinite(e)
+
+
+def test_determinism_fp64(pots):
+    b = synth.water_box(8, 7)
+    e0, ei0, f0 = run(pots["fp64"], b)
+    e1, ei1, f1 = run(pots["fp64"], b)
+    assert np.array_equal(ei0, ei1) and e0 == e1
+    np.testing.assert_allclose(f1, f0, rtol=0, atol=1e-13 * np.sqrt(np.mean(f0 ** 2)))
+
+
+def test_batch_equals_single(pots):
+    boxes = [synth.water_box(4, 40), synth.water_box(5, 41), synth.water_box(4, 42)]
+    import torch
+
+    pot = pots["fp64"]
+    pos = torch.tensor(np.concatenate([b.pos for b in boxes]), dtype=torch.float64, device="cuda")
+    types = torch.tensor(np.concatenate([b.types for b in boxes]), dtype=torch.int32, device="cuda")
+    offs = np.cumsum([0] + [b.n_atoms for b in boxes])
+    eb, ei, f = pot.compute_batch(pos, types, offs, np.stack([b.box for b in boxes]))
+    for k, b in enumerate(boxes):
+        e1, ei1, f1 = run(pot, b)
+        assert eb[k].item() == pytest.approx(e1, rel=1e-13)
+        np.testing.assert_allclose(ei[offs[k]:offs[k + 1]].cpu().numpy(), ei1, rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose(f[offs[k]:offs[k + 1]].cpu().numpy(), f1, rtol=1e-11, atol=1e-12)
