@@ -1,0 +1,178 @@
+#!/usr/bin/env python
+"""Throughput of the Behler-Parrinello energy+force path on one MI355X.
+
+One step = one full evaluation of the 2,044,416-atom synthetic water box
+(681,472 molecules on an 88^3 jittered lattice, 273.24 A, seed 22): wrap +
+cell binning + neighbour-list rebuild + radial/angular symmetry functions +
+per-element networks + dE/dG + force scatter + energy sum, through the C ABI
+(nnp_compute).  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line:  metric/value (atom-steps/s of the FP32 form), the
+roofline of the dominant kernel (the force pass) from HIP events recorded on
+the library's stream during the timed steps and the library's own exact work
+counts, the other arithmetic forms at the same size, and the FP64 CPU oracle
+timed on a bounded sample of the same workload on this host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "atom-steps/s energy+forces, 2M-atom water; FP32 vs BF16-MFMA at force RMSE"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_fp32_2M_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("k_triplet.inc", "common.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2002_00054_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def time_form(pot, pos, types, box, steps, warmup):
+    """ms per step over `steps` calls and per-stage HIP-event times (ms, mean)."""
+    import torch
+
+    for _ in range(warmup):
+        pot.compute(pos, types, box, atom_energy=False)
+    pot.set_profiling(True)
+    stages = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pot.compute(pos, types, box, atom_energy=False)
+        for k, v in pot.timings().items():
+            stages[k] = stages.get(k, 0.0) + v
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pot.set_profiling(False)
+    return 1e3 * dt / steps, {k: v / steps for k, v in stages.items()}
+
+
+def cpu_baseline(table, nets, budget_s=12.0):
+    """The FP64 oracle on a 12,288-atom box of the same generator and density."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle
+    from paper_2002_00054_amd import synth
+
+    pot = oracle.Potential(table, nets)
+    b = synth.water_box(16, 11)
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        pot.compute(b.pos, b.types, b.box, use_cells=True)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_start > budget_s or len(times) >= 10:
+            break
+    times.sort()
+    med = times[len(times) // 2]
+    return {
+        "value": b.n_atoms / med,
+        "unit": "atom-steps/s",
+        "cores": oracle.max_threads(),
+        "kind": "oracle",
+        "sample": f"median of {len(times)} full energy+force evaluations (cell-list neighbours) of a "
+                  f"12,288-atom water box (lattice side 16, seed 11; same generator, density and cutoff "
+                  f"as the 2,044,416-atom workload), FP64 C++ oracle with OpenMP",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n-side", type=int, default=88, help="lattice side (atoms = 3 n^3)")
+    ap.add_argument("--seed", type=int, default=22)
+    ap.add_argument("--forms", default="fp64", help="extra forms timed beside FP32 (comma list, '' for none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (the spatial decomposition "
+              "over several GPUs is a design note, not code); use --gpus 1", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2002_00054_amd import opcount, synth
+    from paper_2002_00054_amd.nnp import Potential
+
+    table, nets = synth.water_table_scaled(), synth.water_nets()
+    b = synth.water_box(args.n_side, args.seed)
+    n = b.n_atoms
+    dev = torch.device("cuda:0")
+    types = torch.tensor(b.types, dtype=torch.int32, device=dev)
+    pos32 = torch.tensor(b.pos, dtype=torch.float32, device=dev)
+    print(f"# workload: {n} atoms, box {b.box[0]:.2f} A", file=sys.stderr, flush=True)
+
+    pot = Potential(table, nets, precision="fp32")
+    ms, stages = time_form(pot, pos32, types, b.box, args.steps, args.warmup)
+    print(f"# fp32: {ms:.3f} ms/step, stages {stages}", file=sys.stderr, flush=True)
+    counts = pot.count_work(pos32, types, b.box)
+    f_force = opcount.flops(opcount.FORCE, counts)
+    f_sf = opcount.flops(opcount.SF, counts)
+    force_ms = stages.get("force", float("nan"))
+    sf_ms = stages.get("sf", float("nan"))
+    achieved = f_force / (force_ms * 1e-3) / 1e12
+    peak = opcount.PEAK_FP32_VECTOR_TFLOPS
+    traffic = None
+    src = kernel_source_hash()
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("source_hash") == src:
+            traffic = tr.get("bytes_per_launch")
+
+    forms = {}
+    for form in [f for f in args.forms.split(",") if f]:
+        p2 = Potential(table, nets, precision=form)
+        x = pos32 if p2.dtype == torch.float32 else torch.tensor(b.pos, dtype=p2.dtype, device=dev)
+        ms2, st2 = time_form(p2, x, types, b.box, max(2, args.steps // 3), 1)
+        forms[form] = {"value": n / (ms2 * 1e-3), "ms_per_step": ms2, "stages_ms": st2}
+        print(f"# {form}: {ms2:.3f} ms/step", file=sys.stderr, flush=True)
+        p2.close()
+        del x
+        torch.cuda.empty_cache()
+
+    out = {
+        "metric": METRIC,
+        "value": n / (ms * 1e-3),
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"water box {n} atoms ({n // 3} H2O, lattice side {args.n_side}, "
+                               f"L={b.box[0]:.2f} A, seed {args.seed}), rc 6 A, H 27 / O 30 SFs, "
+                               f"nets SF-25-25-1 tanh, neighbour list rebuilt every step",
+                   "form": "FP32 plain"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic, "kernel": "k_triplet<FP32, force>",
+                     "flops_per_launch": f_force, "ms_per_launch": force_ms},
+        "stages_ms": stages,
+        "work_counts": counts,
+        "sf_kernel": {"flops_per_launch": f_sf, "ms_per_launch": sf_ms,
+                      "achieved": f_sf / (sf_ms * 1e-3) / 1e12 if sf_ms == sf_ms else None},
+        "forms": forms,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(table, nets)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -68,7 +68,7 @@ typedef enum { NNP_FP64 = 0, NNP_FP32 = 1, NNP_BF16_MIXED = 2 } nnp_precision;
  *            3 = narrow angular G3 (unordered neighbour-element pair nbr[0], nbr[1])
  *  eta       Gaussian exponent, A^-2, >= 0
  *  rs        radial shift, A (G2 only; must be 0 for G3)
- *  zeta      integer-valued exponent in [1, 64] (G3 only)
+ *  zeta      exponent, one of 1, 2, 4, 8, 16, 32 (G3 only)
  *  lambda    +1 or -1 (G3 only)
  *  rc        cutoff radius, A; every entry of one table must use the same rc
  *  shift, scale  centring/scaling: the network sees (G - shift) / scale, scale != 0
@@ -182,6 +182,22 @@ nnp_status nnp_get_params(const nnp_handle* h, double* flat_params_host);
  */
 nnp_status nnp_set_profiling(nnp_handle* h, int enable);
 int nnp_last_timings(const nnp_handle* h, const char** names, double* ms, int max_k);
+
+/*
+ * Work counts of one evaluation of a structure (same arguments as
+ * nnp_compute, no energies or forces), written to host counts[5]:
+ *  [0] neighbour entries of the full lists (each unordered pair within rc twice);
+ *  [1] unordered pairs (j, k) of neighbours of a centre in element-pair classes
+ *      for which the centre has angular SFs (the candidate triplets);
+ *  [2] those with r_jk < rc (the triplet terms of the angular loop, Sec. 3.1);
+ *  [3] angular SF-term updates: each triplet term times the number of angular
+ *      SFs of its (centre, neighbour-pair) class;
+ *  [4] radial SF-term updates: each neighbour entry times the number of radial
+ *      SFs of its (centre, neighbour) element pair.
+ * Used to state algorithmic work per launch.  Synchronises the stream.
+ */
+nnp_status nnp_count_work(nnp_handle* h, int64_t n_atoms, const void* pos, const int32_t* types,
+                          const double box[3], int64_t counts[5], void* stream);
 
 /* Neighbour capacity (slots per atom) currently allocated. */
 int nnp_neighbor_capacity(const nnp_handle* h);

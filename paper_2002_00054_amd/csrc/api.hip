@@ -31,7 +31,7 @@ struct nnp_handle {
   int device = 0;
   std::string err;
   double rc = 0.0;
-  int ne_tmpl = 2;                      // template bound of distinct angular eta (2 or 4)
+  int variant = 0;                      // triplet-kernel instantiation (see launch_mode)
   std::vector<int> n_sf;                // per element
   std::vector<std::vector<int>> sizes;  // per element layer widths
   std::vector<double> params;           // flat caller layout
@@ -131,22 +131,6 @@ nnp_status stage(nnp_handle* h, size_t bytes) {
   return NNP_OK;
 }
 
-// Taylor coefficients in s = r^2 of fc = (1 + cos(pi sqrt(s)/rc))/2 and of dfc/ds.
-void cutoff_coefficients(double rc, double* c, double* d, int deg_max) {
-  long double a = 1.0L;  // (pi/rc)^(2n) / (2n)!
-  const long double q = (long double)M_PI / (long double)rc;
-  std::vector<long double> f(deg_max + 2, 0.0L);
-  f[0] = 1.0L;
-  for (int n = 1; n <= deg_max + 1; ++n) {
-    a *= q * q / ((long double)(2 * n - 1) * (long double)(2 * n));
-    f[n] = 0.5L * ((n & 1) ? -a : a);
-  }
-  for (int n = 0; n <= deg_max; ++n) {
-    c[n] = (double)f[n];
-    d[n] = (double)((long double)(n + 1) * f[n + 1]);
-  }
-}
-
 template <class T>
 DevTab<T> convert_tab(const DevTab<double>& s) {
   DevTab<T> t;
@@ -154,10 +138,7 @@ DevTab<T> convert_tab(const DevTab<double>& s) {
   t.n_el = s.n_el;
   for (int e = 0; e < MAX_EL; ++e) t.n_sf[e] = s.n_sf[e];
   t.rc2 = (T)s.rc2;
-  for (int n = 0; n <= FC_DEG_MAX; ++n) {
-    t.fc_c[n] = (T)s.fc_c[n];
-    t.fc_d[n] = (T)s.fc_d[n];
-  }
+  t.inv_rc2 = (T)s.inv_rc2;
   for (int e = 0; e < MAX_EL; ++e) {
     for (int f = 0; f < MAX_EL; ++f) {
       t.rad_cnt[e][f] = s.rad_cnt[e][f];
@@ -175,9 +156,7 @@ DevTab<T> convert_tab(const DevTab<double>& s) {
     for (int c = 0; c < MAX_CLS; ++c) {
       t.ang_cnt[e][c] = s.ang_cnt[e][c];
       for (int k = 0; k < MAX_ANG; ++k) {
-        t.ang_eta[e][c][k] = s.ang_eta[e][c][k];
-        t.ang_zeta[e][c][k] = s.ang_zeta[e][c][k];
-        t.ang_lam[e][c][k] = s.ang_lam[e][c][k];
+        t.ang_bit[e][c][k] = s.ang_bit[e][c][k];
         t.ang_pre[e][c][k] = (T)s.ang_pre[e][c][k];
         t.ang_out[e][c][k] = s.ang_out[e][c][k];
       }
@@ -453,12 +432,12 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
     if ((st = build_neighbors(h, cm, stream))) return st;
     mk.mark("neighbors");
     TripArgs<P> ta = trip_args<P>(h, cm);
-    const size_t lds = triplet_lds_bytes<P>(1, h->ne_tmpl, h->cap);
+    const size_t lds = triplet_lds_bytes<P>(1, h->variant, h->cap);
     if (lds > lds_limit())
       return fail(h, NNP_E_ARG, "neighbour capacity " + std::to_string(h->cap) + " needs " + std::to_string(lds) +
                                     " bytes of LDS per workgroup, more than the device allows");
     ta.G = G;
-    launch_triplet<P>(0, h->ne_tmpl, ta, stream);
+    launch_triplet<P>(0, h->variant, ta, stream);
     mk.mark("sf");
     MlpArgs<P> ma;
     std::memset(&ma, 0, sizeof(ma));
@@ -470,12 +449,12 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
     ma.Ei = Ei_s;
     ma.nets = reinterpret_cast<const T*>(h->d_nets);
     ma.tab = ta.tab;
+    launch_fill<FAcc>(F_s, n * 3, FAcc(0), stream);
     launch_mlp<P>(ma, stream);
     mk.mark("mlp");
-    launch_fill<FAcc>(F_s, n * 3, FAcc(0), stream);
     ta.C = C;
     ta.F = F_s;
-    launch_triplet<P>(1, h->ne_tmpl, ta, stream);
+    launch_triplet<P>(1, h->variant, ta, stream);
     mk.mark("force");
     launch_unpermute<IO, FAcc>(n, cm.bin.perm, Ei_s, F_s, Ei_o, reinterpret_cast<IO*>(ei_v),
                                reinterpret_cast<IO*>(f_v), stream);
@@ -534,16 +513,16 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
     if ((st = build_neighbors(h, cm, stream))) return st;
     mk.mark("neighbors");
     TripArgs<P> ta = trip_args<P>(h, cm);
-    if (triplet_lds_bytes<P>(2, h->ne_tmpl, h->cap) > lds_limit())
+    if (triplet_lds_bytes<P>(2, h->variant, h->cap) > lds_limit())
       return fail(h, NNP_E_ARG, "neighbour capacity " + std::to_string(h->cap) + " needs more LDS than the device allows");
     ta.G = G;
-    launch_triplet<P>(0, h->ne_tmpl, ta, stream);
+    launch_triplet<P>(0, h->variant, ta, stream);
     mk.mark("sf");
     if (dLdF) launch_permute_rows3<IO>(n, cm.bin.perm, dLdF, delta, stream);
     else launch_fill<IO>(delta, n * 3, IO(0), stream);
     ta.delta = delta;
     ta.V = V;
-    launch_triplet<P>(2, h->ne_tmpl, ta, stream);
+    launch_triplet<P>(2, h->variant, ta, stream);
     mk.mark("jvp");
     launch_gather_struct_grad(n, cm.bin.perm, cm.d_soff, n_struct, dL_dE, gE_atom, stream);
     WGradArgs<P> wa;
@@ -585,6 +564,7 @@ nnp_status build_table(nnp_handle* h, int n_el, int n_sf, const nnp_sf* sf, cons
   h->rc = 0.0;
   std::vector<std::vector<double>> etas(n_el);
   std::vector<int> count(n_el, 0);
+  uint64_t qn_mask = 0;
   for (int s = 0; s < n_sf; ++s) {
     const nnp_sf& d = sf[s];
     const std::string at = "sf[" + std::to_string(s) + "]: ";
@@ -613,8 +593,10 @@ nnp_status build_table(nnp_handle* h, int n_el, int n_sf, const nnp_sf* sf, cons
       t.rad_out[e][f][q] = k;
     } else {
       if (d.rs != 0.0) return fail(nullptr, NNP_E_ARG, at + "rs must be 0 for angular SFs");
-      if (d.zeta != std::floor(d.zeta) || d.zeta < 1 || d.zeta > 64)
-        return fail(nullptr, NNP_E_ARG, at + "zeta must be an integer in [1, 64]");
+      int kz = -1;
+      for (int k = 0; k < 6; ++k)
+        if (d.zeta == (double)(1 << k)) kz = k;
+      if (kz < 0) return fail(nullptr, NNP_E_ARG, at + "zeta must be one of 1, 2, 4, 8, 16, 32");
       if (d.lambda != 1.0 && d.lambda != -1.0) return fail(nullptr, NNP_E_ARG, at + "lambda must be +1 or -1");
       const int e1 = std::min(d.nbr[0], d.nbr[1]), e2 = std::max(d.nbr[0], d.nbr[1]);
       const int cls = class_index(e1, e2, n_el);
@@ -629,9 +611,9 @@ nnp_status build_table(nnp_handle* h, int n_el, int n_sf, const nnp_sf* sf, cons
         ei = (int)etas[e].size();
         etas[e].push_back(d.eta);
       }
-      t.ang_eta[e][cls][q] = ei;
-      t.ang_zeta[e][cls][q] = (int)d.zeta;
-      t.ang_lam[e][cls][q] = d.lambda > 0 ? 1 : -1;
+      const int qb = (d.lambda > 0 ? 0 : 6) + kz;
+      t.ang_bit[e][cls][q] = qb * MAX_NE + ei;
+      qn_mask |= qn_bit(qb, ei);
       t.ang_pre[e][cls][q] = std::pow(2.0, 1.0 - d.zeta);
       t.ang_out[e][cls][q] = k;
     }
@@ -646,9 +628,11 @@ nnp_status build_table(nnp_handle* h, int n_el, int n_sf, const nnp_sf* sf, cons
     }
     ne_max = std::max(ne_max, t.n_eta[e]);
   }
-  h->ne_tmpl = ne_max <= 2 ? 2 : 4;
+  if (ne_max > 2) h->variant = 2;
+  else if ((qn_mask & ~QN_WATER) == 0) h->variant = 0;
+  else h->variant = 1;
   t.rc2 = h->rc * h->rc;
-  cutoff_coefficients(h->rc, t.fc_c, t.fc_d, FC_DEG_MAX);
+  t.inv_rc2 = 1.0 / t.rc2;
   h->n_sf = count;
   // networks
   h->sizes.clear();
@@ -737,6 +721,45 @@ nnp_status nnp_create(int n_el, const char* const* elements, int n_sf, const nnp
   if (hipHostMalloc((void**)&h->h_energy, sizeof(double), hipHostMallocDefault) != hipSuccess)
     return bail(fail(h, NNP_E_NOMEM, "pinned energy"));
   *out = h;
+  return NNP_OK;
+}
+
+nnp_status nnp_count_work(nnp_handle* h, int64_t n_atoms, const void* pos, const int32_t* types, const double box[3],
+                          int64_t counts[5], void* stream) {
+  if (!h) return NNP_E_ARG;
+  h->err.clear();
+  if (!counts || !box || n_atoms < 0) return fail(h, NNP_E_ARG, "bad arguments");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t offs[2] = {0, n_atoms};
+  Common cm;
+  nnp_status st;
+  if ((st = make_batch(h, 1, offs, box, cm.B))) return st;
+  if (n_atoms > 0 && (!pos || !types)) return fail(h, NNP_E_ARG, "pos and types must not be NULL");
+  h->cap = initial_cap(h, cm.B);
+  (void)hipGetLastError();
+  if (h->prec == NNP_FP64) st = prepare<double>(h, cm, (const double*)pos, types, s);
+  else st = prepare<float>(h, cm, (const float*)pos, types, s);
+  if (st) return st;
+  CountTab ct;
+  std::memset(&ct, 0, sizeof(ct));
+  for (int e = 0; e < MAX_EL; ++e) {
+    for (int c = 0; c < MAX_CLS; ++c) ct.ang[e][c] = h->tab_d.ang_cnt[e][c];
+    for (int f = 0; f < MAX_EL; ++f) ct.rad[e][f] = h->tab_d.rad_cnt[e][f];
+  }
+  unsigned long long* d_cnt;
+  if ((st = ensure_t(h, "counts", 8, &d_cnt))) return st;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    if ((st = build_neighbors(h, cm, s))) return st;
+    launch_fill_int(reinterpret_cast<int*>(d_cnt), 16, 0, s);
+    launch_count_terms(cm.bin, cm.nbr, cm.nnb, h->cap, ct, h->rc, d_cnt, s);
+    if ((st = check_launch(h, "count"))) return st;
+    const int r = check_flags(h, s, cm, &st);
+    if (r < 0) return st;
+    if (r == 0) break;
+  }
+  unsigned long long c[8];
+  NNP_HIP(h, hipMemcpy(c, d_cnt, sizeof(c), hipMemcpyDeviceToHost));
+  for (int i = 0; i < 5; ++i) counts[i] = (int64_t)c[i];
   return NNP_OK;
 }
 

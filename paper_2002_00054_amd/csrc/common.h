@@ -39,10 +39,7 @@ struct DevTab {
   int n_el;
   int n_sf[MAX_EL];
   T rc2;                               // rc^2
-  // fc(r) = sum_n fc_c[n] s^n with s = r^2 for r < rc (Taylor series of
-  // (1 + cos(pi sqrt(s)/rc))/2 in s), and dfc/ds = sum_n fc_d[n] s^n.
-  T fc_c[FC_DEG_MAX + 1];
-  T fc_d[FC_DEG_MAX + 1];
+  T inv_rc2;                           // 1 / rc^2
   // radial SFs, per (centre e, neighbour element f)
   int rad_cnt[MAX_EL][MAX_EL];
   T rad_eta[MAX_EL][MAX_EL][MAX_RAD];
@@ -52,11 +49,12 @@ struct DevTab {
   int n_eta[MAX_EL];
   T aeta[MAX_EL][MAX_NE];              // eta
   T aeta2[MAX_EL][MAX_NE];             // eta * log2(e)
-  // angular SFs, per (centre e, neighbour-pair class c)
+  // angular SFs, per (centre e, neighbour-pair class c).  Each SF is the
+  // product of a basis function (1 + lambda cos)^zeta, basis index
+  // q = 6 [lambda < 0] + log2 zeta, with a radial factor of exponent index n;
+  // ang_bit = q * MAX_NE + n.
   int ang_cnt[MAX_EL][MAX_CLS];
-  int ang_eta[MAX_EL][MAX_CLS][MAX_ANG];   // index into aeta[e]
-  int ang_zeta[MAX_EL][MAX_CLS][MAX_ANG];
-  int ang_lam[MAX_EL][MAX_CLS][MAX_ANG];   // +1 / -1
+  int ang_bit[MAX_EL][MAX_CLS][MAX_ANG];
   T ang_pre[MAX_EL][MAX_CLS][MAX_ANG];     // 2^(1 - zeta)
   int ang_out[MAX_EL][MAX_CLS][MAX_ANG];
   // centring / scaling of the network inputs (applied in FP64 to the sums)
@@ -121,37 +119,75 @@ template <class T> struct FcDeg;
 template <> struct FcDeg<float> { static constexpr int v = 9; };
 template <> struct FcDeg<double> { static constexpr int v = 14; };
 
-// Cutoff coefficients held in registers for the lifetime of a kernel.
+// Coefficient a_n of fc = (1 + cos(pi sqrt(t)))/2 = sum_n a_n t^n, t = r^2/rc^2:
+// a_0 = 1, a_n = (-1)^n pi^(2n) / (2 (2n)!) for n >= 1.
+__host__ __device__ constexpr double fc_coef(int n) {
+  if (n == 0) return 1.0;
+  double a = 0.5;
+  const double pi2 = 9.8696044010893586188;  // pi^2
+  for (int k = 1; k <= n; ++k) a *= -pi2 / ((2.0 * k - 1.0) * (2.0 * k));
+  return a;
+}
+
+// Cosine cutoff as a polynomial in s = r^2 with compile-time coefficients
+// (no square root or cosine per evaluation); exactly 0 for s >= rc^2.
 template <class T>
 struct Cutoff {
   static constexpr int D = FcDeg<T>::v;
-  T c[D + 1], d[D];
-  T rc2;
+  T rc2, inv_rc2;
   __device__ inline void load(const DevTab<T>* tab) {
-#pragma unroll
-    for (int n = 0; n <= D; ++n) c[n] = tab->fc_c[n];
-#pragma unroll
-    for (int n = 0; n < D; ++n) d[n] = tab->fc_d[n];
     rc2 = tab->rc2;
+    inv_rc2 = tab->inv_rc2;
   }
-  // fc and dfc/ds at s = r^2 (Horner); exactly 0 for s >= rc^2.
+  // fc and dfc/ds at s = r^2.
   __device__ inline void eval(T s, T& fc, T& dfc_ds) const {
-    T f = c[D], g = d[D - 1];
+    const T t = s * inv_rc2;
+    T f = T(fc_coef(D)), g = T(D * fc_coef(D));
 #pragma unroll
-    for (int n = D - 1; n >= 0; --n) f = f * s + c[n];
-#pragma unroll
-    for (int n = D - 2; n >= 0; --n) g = g * s + d[n];
+    for (int n = D - 1; n >= 1; --n) {
+      f = f * t + T(fc_coef(n));
+      g = g * t + T(n * fc_coef(n));
+    }
+    f = f * t + T(1);
     const bool in = s < rc2;
     fc = in ? f : T(0);
-    dfc_ds = in ? g : T(0);
+    dfc_ds = in ? g * inv_rc2 : T(0);
   }
   __device__ inline T value(T s) const {
-    T f = c[D];
+    const T t = s * inv_rc2;
+    T f = T(fc_coef(D));
 #pragma unroll
-    for (int n = D - 1; n >= 0; --n) f = f * s + c[n];
+    for (int n = D - 1; n >= 0; --n) f = f * t + T(fc_coef(n));
     return s < rc2 ? f : T(0);
   }
 };
+
+// ------------------------------------------------------- angular basis
+// Basis functions B_q(cos) = (1 + lambda cos)^zeta for lambda = +1 (q = k) and
+// lambda = -1 (q = 6 + k), zeta = 2^k, k = 0..5.  A table's use of (q, n)
+// pairs (basis function times radial factor of eta index n) is a bit mask;
+// kernels are instantiated for a mask, so unused pairs cost nothing.
+constexpr int NQ = 12;
+__host__ __device__ constexpr int q_lambda(int q) { return q < 6 ? 1 : -1; }
+__host__ __device__ constexpr int q_k(int q) { return q % 6; }
+__host__ __device__ constexpr int q_zeta(int q) { return 1 << (q % 6); }
+__host__ __device__ constexpr uint64_t qn_bit(int q, int n) { return 1ull << (q * MAX_NE + n); }
+__host__ __device__ constexpr bool qn_used(uint64_t mask, int q, int n) { return (mask >> (q * MAX_NE + n)) & 1ull; }
+__host__ __device__ constexpr bool q_used(uint64_t mask, int q) {
+  return ((mask >> (q * MAX_NE)) & ((1ull << MAX_NE) - 1)) != 0;
+}
+// Largest k used for the basis functions of sign s (0: lambda = +1, 1: -1), -1 if none.
+__host__ __device__ constexpr int k_max(uint64_t mask, int s) {
+  int m = -1;
+  for (int k = 0; k < 6; ++k)
+    if (q_used(mask, 6 * s + k)) m = k;
+  return m;
+}
+// The angular structure of the water table: (lambda, zeta, eta index) =
+// (+1,1,0), (-1,1,0), (+1,4,0), (-1,4,0), (+1,2,1), (+1,16,1).
+constexpr uint64_t QN_WATER = qn_bit(0, 0) | qn_bit(6, 0) | qn_bit(2, 0) | qn_bit(8, 0) | qn_bit(1, 1) | qn_bit(4, 1);
+constexpr uint64_t QN_ALL2 = 0x333333333333ull;  // every q with n < 2
+constexpr uint64_t QN_ALL4 = 0xffffffffffffull;  // every q with n < 4
 
 // x^n for a wave-uniform integer n >= 0 (binary powering; 0^0 = 1).
 template <class T>

@@ -10,6 +10,8 @@
 // Sorted atoms of one element are contiguous, so every workgroup works on
 // rows of a single element and reads that element's weights with uniform
 // loads.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace nnp {
@@ -35,64 +37,164 @@ __device__ inline bool element_tile(int b, int rows, int n_el, const int* __rest
 __device__ inline float tanh_t(float x) { return tanhf(x); }
 __device__ inline double tanh_t(double x) { return tanh(x); }
 
-// One thread per atom, VALU FMAs (forward + input gradient).
+// ------------------------------------------------------------------ MFMA
+// Network forward + input gradient on the matrix cores, one 16-atom tile per
+// wave step.  Activations are kept transposed (units x atoms) and used as the
+// B operand, weights as the A operand, so the accumulator layout of one layer
+// is directly the B operand of the next layer: no LDS transposes.  Each lane
+// carries 8 values of a 32-wide vector; slot s = 4 t + r of lane group
+// g = lane / 16 stands for unit kin_acc(g, s) (accumulator order: the FP32
+// 16x16 accumulators hold rows 4 g + r of tile t, the FP64 ones rows g + 4 r,
+// as measured on gfx950) or for unit 8 g + s (the input rows read from G~).
+// Any bijection works for the reduction as long as the A operand uses the
+// same one.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <class T>
+__device__ inline int kin_acc(int g, int s) {
+  if constexpr (sizeof(T) == 8) return 16 * (s >> 2) + g + 4 * (s & 3);
+  else return 16 * (s >> 2) + 4 * g + (s & 3);
+}
+__device__ inline int kin_row(int g, int s) { return 8 * g + s; }
+
+__device__ inline f32x4 mfma4(float a, float b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ inline f64x4 mfma4(double a, double b, f64x4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+template <class T> struct Acc4;
+template <> struct Acc4<float> { using type = f32x4; };
+template <> struct Acc4<double> { using type = f64x4; };
+
+// y = W x for one tile with 16x16x4 MFMA (FP32 or FP64).  w(o, k) gives the
+// weight of output unit o and input unit k; in_row selects the input slot map.
+template <class T, class WF>
+__device__ inline void layer_k4(const T (&in)[8], bool in_row, WF w, T (&out)[8]) {
+  using V = typename Acc4<T>::type;
+  const int lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    V acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int s = 0; s < 8; ++s) acc = mfma4(w(16 * t + col, in_row ? kin_row(g, s) : kin_acc<T>(g, s)), in[s], acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[4 * t + r] = acc[r];
+  }
+}
+
+// y = W x with 16x16x32 BF16 MFMA and FP32 accumulation; split = BF16x3
+// (x = x_hi + x_lo, W = W_hi + W_lo, products hi*hi + hi*lo + lo*hi).
+template <class WF>
+__device__ inline void layer_bf16(const float (&in)[8], bool in_row, WF w, bool split, float (&out)[8]) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
+  bf16x8 bh, bl;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const __bf16 h = (__bf16)in[s];
+    bh[s] = h;
+    bl[s] = (__bf16)(in[s] - (float)h);
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    bf16x8 ah, al;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const float x = w(16 * t + col, in_row ? kin_row(g, s) : kin_acc<float>(g, s));
+      const __bf16 h = (__bf16)x;
+      ah[s] = h;
+      al[s] = (__bf16)(x - (float)h);
+    }
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+    if (split) {
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[4 * t + r] = acc[r];
+  }
+}
+
+template <int P, class T, class WF>
+__device__ inline void layer(const T (&in)[8], bool in_row, WF w, bool first, T (&out)[8]) {
+  if constexpr (P == P_BF16) layer_bf16(in, in_row, w, first, out);
+  else layer_k4<T>(in, in_row, w, out);
+}
+
+// Grid: n_el x wpe workgroups of 4 waves; workgroup (e, b) serves element e,
+// its waves striding over that element's 16-atom tiles.  The element's
+// padded weights are staged in LDS once per workgroup.
 template <int P>
-__global__ void __launch_bounds__(256) k_mlp_valu(MlpArgs<P> a) {
+__global__ void __launch_bounds__(256) k_mlp_mfma(MlpArgs<P> a, int wpe) {
   using T = typename Types<P>::T;
   using IO = typename Types<P>::IO;
-  int e;
-  int64_t r0, r1;
-  if (!element_tile(blockIdx.x, 256, a.n_el, a.eoff, e, r0, r1)) return;
-  e = uniform(e);
-  const int64_t r = r0 + threadIdx.x;
-  if (r >= r1) return;
-  const T* __restrict__ W = a.nets + (size_t)e * NET_STRIDE;
-  T x[HID], h1[HID], h2[HID];
+  __shared__ T W[NET_STRIDE];
+  __shared__ T isc[HID];
+  const int e = uniform(blockIdx.x / wpe);
+  const int b = blockIdx.x % wpe;
+  if (e >= a.n_el) return;
+  const T* __restrict__ src = a.nets + (size_t)e * NET_STRIDE;
+  for (int i = threadIdx.x; i < NET_STRIDE; i += 256) W[i] = src[i];
+  if (threadIdx.x < HID) isc[threadIdx.x] = threadIdx.x < MAX_SF ? (T)a.tab->inv_scale_d[e][threadIdx.x] : T(0);
+  __syncthreads();
+  const int64_t lo = a.eoff[e], hi = a.eoff[e + 1];
+  const int64_t ntiles = (hi - lo + 15) / 16;
+  const int lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
+  const int wv = threadIdx.x >> 6;
+  T b1[8], b2[8], w3[8];
 #pragma unroll
-  for (int k = 0; k < HID; ++k) x[k] = (T)a.G[r * LD + k];
-#pragma unroll
-  for (int o = 0; o < HID; ++o) {
-    T z = W[OFF_B1 + o];
-#pragma unroll
-    for (int k = 0; k < HID; ++k) z += W[OFF_W1 + o * HID + k] * x[k];
-    h1[o] = tanh_t(z);
+  for (int s = 0; s < 8; ++s) {
+    const int u = kin_acc<T>(g, s);
+    b1[s] = W[OFF_B1 + u];
+    b2[s] = W[OFF_B2 + u];
+    w3[s] = W[OFF_W3 + u];
   }
+  const T b3 = W[OFF_B3];
+  auto W1 = [&](int o, int k) { return W[OFF_W1 + o * HID + k]; };
+  auto W2 = [&](int o, int k) { return W[OFF_W2 + o * HID + k]; };
+  auto W2t = [&](int o, int k) { return W[OFF_W2 + k * HID + o]; };
+  auto W1t = [&](int o, int k) { return W[OFF_W1 + k * HID + o]; };
+  for (int64_t tile = (int64_t)b * 4 + wv; tile < ntiles; tile += (int64_t)wpe * 4) {
+    const int64_t atom = lo + tile * 16 + col;
+    const bool valid = atom < hi;
+    T x[8];
 #pragma unroll
-  for (int o = 0; o < HID; ++o) {
-    T z = W[OFF_B2 + o];
+    for (int s = 0; s < 8; ++s) x[s] = valid ? (T)a.G[atom * LD + kin_row(g, s)] : T(0);
+    T h1[8], h2[8], d[8], y[8];
+    layer<P>(x, true, W1, true, y);
 #pragma unroll
-    for (int k = 0; k < HID; ++k) z += W[OFF_W2 + o * HID + k] * h1[k];
-    h2[o] = tanh_t(z);
-  }
-  T E = W[OFF_B3];
+    for (int s = 0; s < 8; ++s) h1[s] = tanh_t(y[s] + b1[s]);
+    layer<P>(h1, false, W2, false, y);
+    T pe = T(0);
 #pragma unroll
-  for (int o = 0; o < HID; ++o) E += W[OFF_W3 + o] * h2[o];
-  a.Ei[r] = (IO)E;
-  // backward: d2 = w3 (1 - h2^2) (in h2), d1 = (1 - h1^2) W2^T d2 (in h1)
+    for (int s = 0; s < 8; ++s) {
+      h2[s] = tanh_t(y[s] + b2[s]);
+      pe += w3[s] * h2[s];
+      d[s] = w3[s] * (T(1) - h2[s] * h2[s]);
+    }
+    pe += __shfl_xor(pe, 16, 64);
+    pe += __shfl_xor(pe, 32, 64);
+    if (g == 0 && valid) a.Ei[atom] = (IO)(pe + b3);
+    layer<P>(d, false, W2t, false, y);
 #pragma unroll
-  for (int o = 0; o < HID; ++o) h2[o] = W[OFF_W3 + o] * (T(1) - h2[o] * h2[o]);
+    for (int s = 0; s < 8; ++s) d[s] = y[s] * (T(1) - h1[s] * h1[s]);
+    layer<P>(d, false, W1t, true, y);
+    if (valid) {
 #pragma unroll
-  for (int k = 0; k < HID; ++k) {
-    T s = T(0);
-#pragma unroll
-    for (int o = 0; o < HID; ++o) s += W[OFF_W2 + o * HID + k] * h2[o];
-    x[k] = s * (T(1) - h1[k] * h1[k]);
-  }
-#pragma unroll
-  for (int k = 0; k < HID; ++k) {
-    T s = T(0);
-#pragma unroll
-    for (int o = 0; o < HID; ++o) s += W[OFF_W1 + o * HID + k] * x[o];
-    const T isc = k < MAX_SF ? (T)a.tab->inv_scale_d[e][k] : T(0);
-    a.C[r * LD + k] = (IO)(s * isc);
+      for (int s = 0; s < 8; ++s) {
+        const int k = kin_acc<T>(g, s);
+        a.C[atom * LD + k] = (IO)(y[s] * isc[k]);
+      }
+    }
   }
 }
 
 template <int P>
 void launch_mlp(const MlpArgs<P>& a, hipStream_t stream) {
   if (a.n == 0) return;
-  const unsigned g = (unsigned)((a.n + 255) / 256 + a.n_el);
-  hipLaunchKernelGGL(k_mlp_valu<P>, dim3(g), dim3(256), 0, stream, a);
+  int wpe = (int)std::min<int64_t>(512, (a.n + 63) / 64);
+  if (wpe < 1) wpe = 1;
+  hipLaunchKernelGGL(k_mlp_mfma<P>, dim3((unsigned)(a.n_el * wpe)), dim3(256), 0, stream, a, wpe);
 }
 
 // ------------------------------------------------------------ weight gradient

@@ -197,6 +197,64 @@ __global__ void __launch_bounds__(256) k_neighbors(int64_t n, const double4* __r
   if (total > cap) atomicMax(&flags[1], total);
 }
 
+// Work counts of one evaluation, one thread per centre:
+//   counts[0] neighbour entries (each unordered pair twice),
+//   counts[1] unordered neighbour pairs (j, k) of a centre in element-pair
+//             classes that have angular SFs (candidate triplets),
+//   counts[2] those with r_jk < rc (triplet terms),
+//   counts[3] angular SF-term updates (triplet terms x angular SFs of the class),
+//   counts[4] radial SF-term updates (neighbour entries x radial SFs of the
+//             centre / neighbour element pair).
+__global__ void __launch_bounds__(256) k_count_terms(int64_t n, const double4* __restrict__ pos4,
+                                                     const DevStruct* __restrict__ st, const int* __restrict__ nbr,
+                                                     const int4* __restrict__ nnb, int cap, int n_el, CountTab ct,
+                                                     double rc2, unsigned long long* __restrict__ counts) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const double4 p = pos4[s];
+  const int e = elem_of(p.w);
+  const DevStruct& S = st[struct_of(p.w)];
+  const int4 c4 = nnb[s];
+  const int cnt[MAX_EL] = {c4.x, c4.y, c4.z, c4.w};
+  int off[MAX_EL + 1];
+  off[0] = 0;
+  for (int f = 0; f < MAX_EL; ++f) off[f + 1] = off[f] + (f < n_el ? cnt[f] : 0);
+  const int* row = nbr + s * (int64_t)cap;
+  unsigned long long cand = 0, pass = 0, aterms = 0, rterms = 0;
+  for (int f = 0; f < n_el; ++f) rterms += (unsigned long long)cnt[f] * ct.rad[e][f];
+  for (int e1 = 0; e1 < n_el; ++e1)
+    for (int e2 = e1; e2 < n_el; ++e2) {
+      const int na = ct.ang[e][class_index(e1, e2, n_el)];
+      if (na == 0) continue;
+      unsigned long long pc = 0;
+      for (int a = off[e1]; a < off[e1] + cnt[e1]; ++a) {
+        const double4 qa = pos4[row[a]];
+        double ax = qa.x - p.x, ay = qa.y - p.y, az = qa.z - p.z;
+        ax -= S.L[0] * rint(ax * S.invL[0]);
+        ay -= S.L[1] * rint(ay * S.invL[1]);
+        az -= S.L[2] * rint(az * S.invL[2]);
+        const int b0 = e1 == e2 ? a + 1 : off[e2];
+        for (int b = b0; b < off[e2] + cnt[e2]; ++b) {
+          const double4 qb = pos4[row[b]];
+          double bx = qb.x - p.x, by = qb.y - p.y, bz = qb.z - p.z;
+          bx -= S.L[0] * rint(bx * S.invL[0]);
+          by -= S.L[1] * rint(by * S.invL[1]);
+          bz -= S.L[2] * rint(bz * S.invL[2]);
+          const double wx = bx - ax, wy = by - ay, wz = bz - az;
+          ++cand;
+          if (wx * wx + wy * wy + wz * wz < rc2) ++pc;
+        }
+      }
+      pass += pc;
+      aterms += pc * (unsigned long long)na;
+    }
+  atomicAdd(&counts[0], (unsigned long long)off[n_el]);
+  atomicAdd(&counts[1], cand);
+  atomicAdd(&counts[2], pass);
+  atomicAdd(&counts[3], aterms);
+  atomicAdd(&counts[4], rterms);
+}
+
 // ------------------------------------------------------------ launchers
 template <class TIn>
 void launch_bin_sort(const BinArgs& a, const TIn* pos, hipStream_t stream) {
@@ -227,6 +285,14 @@ void launch_neighbors(const BinArgs& a, double rc, int cap, int* nbr, int4* nnb,
   const unsigned g = (unsigned)((a.n + 255) / 256);
   hipLaunchKernelGGL(k_neighbors, dim3(g), dim3(256), 0, stream, a.n, a.pos4, a.st, a.start, a.n_el,
                      a.total_cells, rc * rc, cap, nbr, nnb, a.flags);
+}
+
+void launch_count_terms(const BinArgs& a, const int* nbr, const int4* nnb, int cap, const CountTab& ct, double rc,
+                        unsigned long long* counts, hipStream_t stream) {
+  if (a.n == 0) return;
+  const unsigned g = (unsigned)((a.n + 255) / 256);
+  hipLaunchKernelGGL(k_count_terms, dim3(g), dim3(256), 0, stream, a.n, a.pos4, a.st, nbr, nnb, cap, a.n_el, ct,
+                     rc * rc, counts);
 }
 
 }  // namespace nnp

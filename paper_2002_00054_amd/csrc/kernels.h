@@ -28,6 +28,13 @@ void launch_fill_int(int* p, int64_t n, int v, hipStream_t stream);
 template <class TIn>
 void launch_bin_sort(const BinArgs& a, const TIn* pos, hipStream_t stream);
 void launch_neighbors(const BinArgs& a, double rc, int cap, int* nbr, int4* nnb, hipStream_t stream);
+// Angular / radial SF counts per (centre, class) and (centre, neighbour element).
+struct CountTab {
+  int ang[MAX_EL][MAX_CLS];
+  int rad[MAX_EL][MAX_EL];
+};
+void launch_count_terms(const BinArgs& a, const int* nbr, const int4* nnb, int cap, const CountTab& ct, double rc,
+                        unsigned long long* counts, hipStream_t stream);
 
 // ---------------------------------------------------------------- K3/K5/K7
 template <int P>

@@ -23,7 +23,7 @@ STATUS = {0: "NNP_OK", -1: "NNP_E_ARG", -2: "NNP_E_BOX", -3: "NNP_E_TYPE", -4: "
 #: Every symbol include/nnp.h declares.
 EXPORTS = ("nnp_create", "nnp_compute", "nnp_compute_batch", "nnp_backward", "nnp_n_params", "nnp_set_params",
            "nnp_get_params", "nnp_set_profiling", "nnp_last_timings", "nnp_neighbor_capacity",
-           "nnp_set_neighbor_capacity", "nnp_destroy", "nnp_last_error")
+           "nnp_set_neighbor_capacity", "nnp_count_work", "nnp_destroy", "nnp_last_error")
 
 
 class NNPError(RuntimeError):
@@ -73,13 +73,14 @@ def load_library(path: str = LIB_PATH):
     L.nnp_last_timings.argtypes = [vp, C.POINTER(C.c_char_p), dp, C.c_int]
     L.nnp_neighbor_capacity.argtypes = [vp]
     L.nnp_set_neighbor_capacity.argtypes = [vp, C.c_int]
+    L.nnp_count_work.argtypes = [vp, i64, vp, vp, dp, C.POINTER(i64), vp]
     L.nnp_destroy.argtypes = [vp]
     L.nnp_destroy.restype = None
     L.nnp_last_error.argtypes = [vp]
     L.nnp_last_error.restype = C.c_char_p
     for name in ("nnp_create", "nnp_compute", "nnp_compute_batch", "nnp_backward", "nnp_set_params",
                  "nnp_get_params", "nnp_set_profiling", "nnp_set_neighbor_capacity", "nnp_last_timings",
-                 "nnp_neighbor_capacity"):
+                 "nnp_neighbor_capacity", "nnp_count_work"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -230,6 +231,17 @@ class Potential:
                                          _ptr(types), bx.ctypes.data_as(C.POINTER(C.c_double)), _ptr(dL_dE),
                                          _ptr(dL_dF), _ptr(g), _stream_ptr(stream)))
         return g
+
+    def count_work(self, pos, types, box, stream=None) -> dict:
+        """Neighbour entries, candidate neighbour pairs and triplet terms of
+        one evaluation (for algorithmic-work accounting)."""
+        pos, types = self._prep(pos, types)
+        boxa = (C.c_double * 3)(*[float(x) for x in box])
+        out = (C.c_int64 * 5)()
+        self._check(self._L.nnp_count_work(self._h, pos.shape[0], _ptr(pos), _ptr(types), boxa, out,
+                                           _stream_ptr(stream)))
+        return {"pairs": int(out[0]), "candidates": int(out[1]), "triplets": int(out[2]),
+                "angular_terms": int(out[3]), "radial_terms": int(out[4])}
 
     def set_params(self, flat):
         import torch

@@ -1,0 +1,174 @@
+"""The two AI-systems forms beside the plain path, on the GPU through the C ABI.
+
+Precision form (NNP_BF16_MIXED): errors against the FP64 oracle on a fresh
+12,288-atom box; the force RMSE must stay within 5e-3 eV/A.
+
+Differentiation form: forces are the adjoint of the energy (gradcheck in
+FP64), and the parameter gradient of the energy+force loss from
+nnp_backward matches the FP64 oracle's gradient (FP64 to 1e-8, FP32 to 1e-4
+relative L2 per layer) and central differences of the GPU loss.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from common import oracle_water, water_potential
+from gpu_common import make_potential, oracle_input, run, say
+from paper_2002_00054_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def test_bf16_form_errors_vs_oracle():
+    b = synth.water_box(16, 12)
+    pot = make_potential("bf16")
+    e, ei, f = run(pot, b)
+    ref = oracle_water().compute(oracle_input(b, "bf16"), b.types, b.box, use_cells=True)
+    de = ei - ref["Ei"]
+    df = f - ref["F"]
+    rmse_f = float(np.sqrt(np.mean(df ** 2)))
+    say(f"bf16 form: E/atom err {abs(e - ref['E']) / b.n_atoms:.3e} eV, Ei rmse {np.sqrt(np.mean(de ** 2)):.3e} "
+        f"max {np.max(np.abs(de)):.3e} eV, F rmse {rmse_f:.3e} max {np.max(np.abs(df)):.3e} eV/A "
+        f"(mean |F| {np.mean(np.abs(ref['F'])):.3e})")
+    assert rmse_f <= 5e-3
+    assert np.max(np.abs(de)) <= 5e-2
+
+
+def test_fp32_mfma_network_matches_oracle_tightly():
+    """The FP32 network on MFMA (not only the SF terms) is within FP32 error."""
+    b = synth.water_box(6, 9)
+    pot = make_potential("fp32")
+    e, ei, f = run(pot, b)
+    ref = oracle_water().compute(oracle_input(b, "fp32"), b.types, b.box)
+    assert np.max(np.abs(ei - ref["Ei"])) < 2e-6
+    assert np.max(np.abs(f - ref["F"])) < 2e-5
+
+
+# ----------------------------------------------------------- differentiation
+def test_energy_gradient_is_minus_force_gradcheck():
+    import torch
+
+    from paper_2002_00054_amd.nnp import energy
+
+    c = synth.water_box(4, 6)
+    pot = make_potential("fp64")
+    pos = torch.tensor(c.pos, dtype=torch.float64, device="cuda", requires_grad=True)
+    types = torch.tensor(c.types, dtype=torch.int32, device="cuda")
+    E = energy(pos, pot, types, c.box)
+    (g,) = torch.autograd.grad(E, pos)
+    _, _, f = pot.compute(pos.detach(), types, c.box)
+    # two evaluations differ only by the order of the force atomics
+    assert torch.allclose(g, -f, rtol=0, atol=1e-12 * f.abs().max().item())
+    # central differences of E through the GPU path on a few coordinates
+    idx = [(0, 0), (5, 2), (77, 1), (191, 0)]
+    for i, a in idx:
+        p = pos.detach().clone()
+        p[i, a] += 1e-5
+        ep = pot.compute(p, types, c.box)[0]
+        p[i, a] -= 2e-5
+        em = pot.compute(p, types, c.box)[0]
+        assert abs((ep - em) / 2e-5 - g[i, a].item()) < 1e-6
+
+
+def _batch(n_boxes=3):
+    sides = [4, 5, 4][:n_boxes]
+    boxes = [synth.water_box(s, 40 + i) for i, s in enumerate(sides)]
+    return boxes
+
+
+def _gpu_loss_and_grad(pot, boxes, Ehat, Fhat, params):
+    import torch
+
+    from paper_2002_00054_amd.nnp import energy_forces
+
+    dt = pot.dtype
+    pos = torch.tensor(np.concatenate([b.pos for b in boxes]), dtype=dt, device="cuda")
+    types = torch.tensor(np.concatenate([b.types for b in boxes]), dtype=torch.int32, device="cuda")
+    offs = np.cumsum([0] + [b.n_atoms for b in boxes])
+    bx = np.stack([b.box for b in boxes])
+    th = torch.tensor(params, dtype=torch.float64, device="cuda", requires_grad=True)
+    E, F = energy_forces(th, pos, pot, types, offs, bx)
+    N = torch.tensor([b.n_atoms for b in boxes], dtype=torch.float64, device="cuda")
+    Eh = torch.tensor(Ehat, dtype=torch.float64, device="cuda")
+    Fh = torch.tensor(Fhat, dtype=dt, device="cuda")
+    L = torch.mean(((E - Eh) / N) ** 2) + 0.1 * torch.sum((F - Fh).double() ** 2) / (3 * N.sum())
+    (g,) = torch.autograd.grad(L, th)
+    return L.item(), g.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def train_setup():
+    table, nets = water_potential()
+    teacher = oracle.Potential(table, synth.teacher_nets())
+    boxes = _batch()
+    Ehat, Fhat = oracle.batch_energy_forces(teacher, boxes)
+    student = oracle.Potential(table, nets)
+    L, g = oracle.loss_and_grad(student, boxes, Ehat, Fhat)
+    return dict(table=table, nets=nets, boxes=boxes, Ehat=Ehat, Fhat=Fhat, L=L, g=g,
+                params=synth.flat_params(nets))
+
+
+def _per_layer_rel(g, ref, nets):
+    out = []
+    o = 0
+    for n in nets:
+        for w, b in zip(n.W, n.b):
+            for sz in (w.size, b.size):
+                a, r = g[o:o + sz], ref[o:o + sz]
+                out.append(np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-300))
+                o += sz
+    return np.array(out)
+
+
+def test_weight_gradient_fp64_matches_oracle(train_setup):
+    s = train_setup
+    pot = make_potential("fp64")
+    L, g = _gpu_loss_and_grad(pot, s["boxes"], s["Ehat"], s["Fhat"], s["params"])
+    assert L == pytest.approx(s["L"], rel=1e-10)
+    rel = _per_layer_rel(g, s["g"], s["nets"])
+    say("fp64 weight-gradient rel-L2 per tensor, max", rel.max())
+    assert rel.max() < 1e-8
+
+
+def test_weight_gradient_fp32_matches_oracle(train_setup):
+    s = train_setup
+    pot = make_potential("fp32")
+    L, g = _gpu_loss_and_grad(pot, s["boxes"], s["Ehat"], s["Fhat"], s["params"])
+    rel = _per_layer_rel(g, s["g"], s["nets"])
+    say("fp32 weight-gradient rel-L2 per tensor, max", rel.max())
+    assert L == pytest.approx(s["L"], rel=1e-4)
+    assert rel.max() < 1e-4
+
+
+def test_weight_gradient_finite_differences_gpu(train_setup):
+    s = train_setup
+    pot = make_potential("fp64")
+    p0 = s["params"].copy()
+    L, g = _gpu_loss_and_grad(pot, s["boxes"], s["Ehat"], s["Fhat"], p0)
+    rng = np.random.default_rng(3)
+    h = 1e-5
+    for k in rng.choice(len(p0), size=12, replace=False):
+        pp = p0.copy()
+        pp[k] += h
+        pm = p0.copy()
+        pm[k] -= h
+        Lp, _ = _gpu_loss_and_grad(pot, s["boxes"], s["Ehat"], s["Fhat"], pp)
+        Lm, _ = _gpu_loss_and_grad(pot, s["boxes"], s["Ehat"], s["Fhat"], pm)
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])) + 1e-9, (k, fd, g[k])
+
+
+def test_position_gradient_of_forces_raises(train_setup):
+    import torch
+
+    from paper_2002_00054_amd.nnp import energy_forces
+
+    s = train_setup
+    pot = make_potential("fp64")
+    b = s["boxes"][0]
+    pos = torch.tensor(b.pos, dtype=torch.float64, device="cuda", requires_grad=True)
+    types = torch.tensor(b.types, dtype=torch.int32, device="cuda")
+    th = torch.tensor(s["params"], dtype=torch.float64, device="cuda", requires_grad=True)
+    E, F = energy_forces(th, pos, pot, types, [0, b.n_atoms], b.box[None])
+    with pytest.raises(NotImplementedError):
+        torch.autograd.grad(F.sum(), pos)
