@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--seed", type=int, default=22)
     ap.add_argument("--forms", default="fp64", help="extra forms timed beside FP32 (comma list, '' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB with a plain device copy (for HBM counter calibration) and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -102,6 +104,14 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        x = torch.ones(args.copy_calibration * 2 ** 18, dtype=torch.float32, device="cuda:0")
+        torch.cuda.synchronize()
+        y = x.clone()
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}), flush=True)
+        return
 
     from paper_2002_00054_amd import opcount, synth
     from paper_2002_00054_amd.nnp import Potential
