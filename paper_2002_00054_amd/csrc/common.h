@@ -87,11 +87,35 @@ __device__ inline int struct_of(double w) { return (int)(__double_as_longlong(w)
 __host__ __device__ inline int class_index(int e1, int e2, int n_el) { return e1 * n_el - e1 * (e1 - 1) / 2 + (e2 - e1); }
 
 // ----------------------------------------------------------- wave helpers
+// Sum over the 64 lanes, returned in every lane: an inclusive scan inside
+// each 16-lane row with DPP row shifts (1, 2, 4, 8; lanes shifted in from
+// outside the row read 0), then the four row totals (lanes 15, 31, 47, 63)
+// read out and added in a fixed order.
+template <int CTRL>
+__device__ inline float dpp_shift(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ inline double dpp_shift(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline float lane_value(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+__device__ inline double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 template <class T>
 __device__ inline T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_shift<0x111>(v);  // row_shr:1
+  v += dpp_shift<0x112>(v);  // row_shr:2
+  v += dpp_shift<0x114>(v);  // row_shr:4
+  v += dpp_shift<0x118>(v);  // row_shr:8
+  return (lane_value(v, 15) + lane_value(v, 31)) + (lane_value(v, 47) + lane_value(v, 63));
 }
 
 __device__ inline int lane_id() { return __lane_id(); }
@@ -112,16 +136,9 @@ __device__ inline float exp_scaled(float /*x_ln*/, float x_log2) { return __buil
 __device__ inline double rsqrt_t(double s) { return 1.0 / sqrt(s); }
 __device__ inline float rsqrt_t(float s) { return __builtin_amdgcn_rsqf(s); }
 
-// Degree of the cutoff polynomial per arithmetic type: the first omitted
-// Taylor term is below 2e-9 (FP32, degree 9) or 2e-18 (FP64, degree 14) on
-// [0, rc^2].
-template <class T> struct FcDeg;
-template <> struct FcDeg<float> { static constexpr int v = 9; };
-template <> struct FcDeg<double> { static constexpr int v = 14; };
-
 // Coefficient a_n of fc = (1 + cos(pi sqrt(t)))/2 = sum_n a_n t^n, t = r^2/rc^2:
-// a_0 = 1, a_n = (-1)^n pi^(2n) / (2 (2n)!) for n >= 1.
-__host__ __device__ constexpr double fc_coef(int n) {
+// a_0 = 1, a_n = (-1)^n pi^(2n) / (2 (2n)!) for n >= 1 (Taylor series).
+__host__ __device__ constexpr double fc_taylor(int n) {
   if (n == 0) return 1.0;
   double a = 0.5;
   const double pi2 = 9.8696044010893586188;  // pi^2
@@ -129,37 +146,61 @@ __host__ __device__ constexpr double fc_coef(int n) {
   return a;
 }
 
+// Cutoff polynomial in t per arithmetic type.  FP64: Taylor series to degree
+// 14 (first omitted term < 2e-18 on [0, 1]).  FP32: degree-6 interpolant at
+// the Chebyshev points (gen_cutoff_fp32.py; max error 5.5e-9, below FP32
+// rounding), three terms shorter than the equivalent Taylor series.
+template <class T> struct FcPoly;
+template <> struct FcPoly<double> {
+  static constexpr int D = 14;
+  static constexpr double a(int n) { return fc_taylor(n); }
+};
+template <> struct FcPoly<float> {
+  static constexpr int D = 6;
+  static constexpr double a(int n) {
+    constexpr double c[7] = {0.99999999447228860, -2.4674005583220304, 2.0293473727609408, -0.66757901115278839,
+                             0.11751451131309654, -0.012679142877827992, 0.00079683910699860207};
+    return c[n];
+  }
+};
+
 // Cosine cutoff as a polynomial in s = r^2 with compile-time coefficients
-// (no square root or cosine per evaluation); exactly 0 for s >= rc^2.
+// (no square root or cosine per evaluation); exactly 0 for s >= rc^2 unless
+// the caller already knows s < rc^2 (the *_in variants).
 template <class T>
 struct Cutoff {
-  static constexpr int D = FcDeg<T>::v;
+  static constexpr int D = FcPoly<T>::D;
   T rc2, inv_rc2;
   __device__ inline void load(const DevTab<T>* tab) {
     rc2 = tab->rc2;
     inv_rc2 = tab->inv_rc2;
   }
-  // fc and dfc/ds at s = r^2.
-  __device__ inline void eval(T s, T& fc, T& dfc_ds) const {
+  // fc and dfc/ds at s = r^2, for s < rc^2.
+  __device__ inline void eval_in(T s, T& fc, T& dfc_ds) const {
     const T t = s * inv_rc2;
-    T f = T(fc_coef(D)), g = T(D * fc_coef(D));
+    T f = T(FcPoly<T>::a(D)), g = T(D * FcPoly<T>::a(D));
 #pragma unroll
     for (int n = D - 1; n >= 1; --n) {
-      f = f * t + T(fc_coef(n));
-      g = g * t + T(n * fc_coef(n));
+      f = f * t + T(FcPoly<T>::a(n));
+      g = g * t + T(n * FcPoly<T>::a(n));
     }
-    f = f * t + T(1);
+    fc = f * t + T(FcPoly<T>::a(0));
+    dfc_ds = g * inv_rc2;
+  }
+  __device__ inline void eval(T s, T& fc, T& dfc_ds) const {
+    eval_in(s, fc, dfc_ds);
     const bool in = s < rc2;
-    fc = in ? f : T(0);
-    dfc_ds = in ? g * inv_rc2 : T(0);
+    fc = in ? fc : T(0);
+    dfc_ds = in ? dfc_ds : T(0);
   }
-  __device__ inline T value(T s) const {
+  __device__ inline T value_in(T s) const {
     const T t = s * inv_rc2;
-    T f = T(fc_coef(D));
+    T f = T(FcPoly<T>::a(D));
 #pragma unroll
-    for (int n = D - 1; n >= 0; --n) f = f * t + T(fc_coef(n));
-    return s < rc2 ? f : T(0);
+    for (int n = D - 1; n >= 0; --n) f = f * t + T(FcPoly<T>::a(n));
+    return f;
   }
+  __device__ inline T value(T s) const { return s < rc2 ? value_in(s) : T(0); }
 };
 
 // ------------------------------------------------------- angular basis
