@@ -161,6 +161,11 @@ DevTab<T> convert_tab(const DevTab<double>& s) {
         t.ang_out[e][c][k] = s.ang_out[e][c][k];
       }
     }
+    for (int c = 0; c < MAX_CLS; ++c)
+      for (int b = 0; b < 12 * MAX_NE; ++b) {
+        t.qn_out[e][c][b] = s.qn_out[e][c][b];
+        t.qn_pre[e][c][b] = (T)s.qn_pre[e][c][b];
+      }
     for (int k = 0; k < MAX_SF; ++k) {
       t.shift_d[e][k] = s.shift_d[e][k];
       t.inv_scale_d[e][k] = s.inv_scale_d[e][k];
@@ -561,6 +566,9 @@ nnp_status build_table(nnp_handle* h, int n_el, int n_sf, const nnp_sf* sf, cons
   DevTab<double>& t = h->tab_d;
   std::memset(&t, 0, sizeof(t));
   t.n_el = n_el;
+  for (int e = 0; e < MAX_EL; ++e)
+    for (int c = 0; c < MAX_CLS; ++c)
+      for (int b = 0; b < 12 * MAX_NE; ++b) t.qn_out[e][c][b] = -1;
   h->rc = 0.0;
   std::vector<std::vector<double>> etas(n_el);
   std::vector<int> count(n_el, 0);
@@ -612,6 +620,10 @@ nnp_status build_table(nnp_handle* h, int n_el, int n_sf, const nnp_sf* sf, cons
         etas[e].push_back(d.eta);
       }
       const int qb = (d.lambda > 0 ? 0 : 6) + kz;
+      if (t.qn_out[e][cls][qb * MAX_NE + ei] >= 0)
+        return fail(nullptr, NNP_E_ARG, at + "duplicate angular SF (same class, eta, zeta and lambda)");
+      t.qn_out[e][cls][qb * MAX_NE + ei] = k;
+      t.qn_pre[e][cls][qb * MAX_NE + ei] = std::pow(2.0, 1.0 - d.zeta);
       t.ang_bit[e][cls][q] = qb * MAX_NE + ei;
       qn_mask |= qn_bit(qb, ei);
       t.ang_pre[e][cls][q] = std::pow(2.0, 1.0 - d.zeta);

@@ -57,6 +57,9 @@ struct DevTab {
   int ang_bit[MAX_EL][MAX_CLS][MAX_ANG];
   T ang_pre[MAX_EL][MAX_CLS][MAX_ANG];     // 2^(1 - zeta)
   int ang_out[MAX_EL][MAX_CLS][MAX_ANG];
+  // the same as a map from (q, n) to the one SF of the class using it (-1: none)
+  int qn_out[MAX_EL][MAX_CLS][12 * MAX_NE];
+  T qn_pre[MAX_EL][MAX_CLS][12 * MAX_NE];
   // centring / scaling of the network inputs (applied in FP64 to the sums)
   double shift_d[MAX_EL][MAX_SF];
   double inv_scale_d[MAX_EL][MAX_SF];
