@@ -101,7 +101,7 @@ typedef struct {
  * afterwards) and uploads the parameters to the current HIP device.
  *  n_el      number of elements, 1..4
  *  elements  [n_el] element names (informational; index = type id), may be NULL
- *  n_sf, sf  the symmetry-function table (see nnp_sf); per element at most 64
+ *  n_sf, sf  the symmetry-function table (see nnp_sf); per element at most 32
  *            entries, per (centre, neighbour element) at most 16 radial, per
  *            (centre, neighbour pair) at most 8 angular, and per centre at most
  *            4 distinct angular eta

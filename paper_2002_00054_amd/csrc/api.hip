@@ -44,6 +44,7 @@ struct nnp_handle {
   // workspace
   std::map<std::string, nnp::DevBuf> ws;
   int cap = 0;                          // neighbour slots per atom
+  int lcap = 0;                         // most neighbours of any atom in the last build, rounded up
   int cap_override = 0;
   // pinned staging for small uploads / readbacks
   void* h_stage = nullptr;
@@ -364,7 +365,7 @@ nnp_status build_neighbors(nnp_handle* h, Common& cm, hipStream_t stream) {
   const int64_t n = std::max<int64_t>(cm.B.n, 1);
   if ((st = ensure_t(h, "nbr", (size_t)n * h->cap, &cm.nbr))) return st;
   if ((st = ensure_t(h, "nnb", n, &cm.nnb))) return st;
-  launch_fill_int(cm.bin.flags + 1, 1, 0, stream);
+  launch_fill_int(cm.bin.flags + 1, 2, 0, stream);
   launch_neighbors(cm.bin, h->rc, h->cap, cm.nbr, cm.nnb, stream);
   return NNP_OK;
 }
@@ -375,6 +376,7 @@ TripArgs<P> trip_args(nnp_handle* h, Common& cm) {
   std::memset(&t, 0, sizeof(t));
   t.n = cm.B.n;
   t.cap = h->cap;
+  t.lcap = h->lcap;
   t.pos4 = cm.bin.pos4;
   t.nbr = cm.nbr;
   t.nnb = cm.nnb;
@@ -383,8 +385,9 @@ TripArgs<P> trip_args(nnp_handle* h, Common& cm) {
   return t;
 }
 
-// Reads back the flags; returns 1 if the neighbour capacity overflowed (cap
-// has been grown), 0 if all is well, <0 on error.
+// Reads back the flags after a neighbour build; returns 1 if the neighbour
+// capacity overflowed (cap has been grown: rebuild), 0 if all is well (lcap
+// then bounds every atom's count), <0 on error.
 int check_flags(nnp_handle* h, hipStream_t stream, Common& cm, nnp_status* st) {
   hipError_t e = hipMemcpyAsync(h->h_flags, cm.bin.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -401,6 +404,8 @@ int check_flags(nnp_handle* h, hipStream_t stream, Common& cm, nnp_status* st) {
     h->cap = (nc + 15) / 16 * 16;
     return 1;
   }
+  const int most = std::max(h->h_flags[2], 1);
+  h->lcap = std::min(h->cap, (most + 7) / 8 * 8);
   return 0;
 }
 
@@ -435,11 +440,14 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
   if ((st = ensure_t(h, "energies", n_struct, &energies))) return st;
   for (int attempt = 0; attempt < 8; ++attempt) {
     if ((st = build_neighbors(h, cm, stream))) return st;
+    const int r = check_flags(h, stream, cm, &st);
+    if (r < 0) return st;
+    if (r > 0) continue;  // capacity grew: rebuild the neighbour list
     mk.mark("neighbors");
     TripArgs<P> ta = trip_args<P>(h, cm);
-    const size_t lds = triplet_lds_bytes<P>(1, h->variant, h->cap);
+    const size_t lds = std::max(triplet_lds_bytes<P>(0, h->variant, h->lcap), triplet_lds_bytes<P>(1, h->variant, h->lcap));
     if (lds > lds_limit())
-      return fail(h, NNP_E_ARG, "neighbour capacity " + std::to_string(h->cap) + " needs " + std::to_string(lds) +
+      return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) + " neighbours needs " + std::to_string(lds) +
                                     " bytes of LDS per workgroup, more than the device allows");
     ta.G = G;
     launch_triplet<P>(0, h->variant, ta, stream);
@@ -470,15 +478,11 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
       NNP_HIP(h, hipMemcpyAsync(h->h_energy, energies, sizeof(double), hipMemcpyDeviceToHost, stream));
     mk.mark("finish");
     if ((st = check_launch(h, "forward"))) return st;
-    const int r = check_flags(h, stream, cm, &st);
-    if (r < 0) return st;
-    if (r == 0) {
-      if (energy_host) *energy_host = *h->h_energy;
-      mk.finish();
-      h->has_forward = true;
-      return NNP_OK;
-    }
-    // capacity grew: rebuild the neighbour list and redo the evaluation
+    NNP_HIP(h, hipStreamSynchronize(stream));
+    if (energy_host) *energy_host = *h->h_energy;
+    mk.finish();
+    h->has_forward = true;
+    return NNP_OK;
   }
   return fail(h, NNP_E_STATE, "neighbour capacity did not converge");
 }
@@ -516,10 +520,15 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
   if ((st = ensure_t(h, "wpad", (size_t)h->n_el * NET_STRIDE, &padded))) return st;
   for (int attempt = 0; attempt < 8; ++attempt) {
     if ((st = build_neighbors(h, cm, stream))) return st;
+    const int r = check_flags(h, stream, cm, &st);
+    if (r < 0) return st;
+    if (r > 0) continue;  // capacity grew: rebuild the neighbour list
     mk.mark("neighbors");
     TripArgs<P> ta = trip_args<P>(h, cm);
-    if (triplet_lds_bytes<P>(2, h->variant, h->cap) > lds_limit())
-      return fail(h, NNP_E_ARG, "neighbour capacity " + std::to_string(h->cap) + " needs more LDS than the device allows");
+    if (std::max(triplet_lds_bytes<P>(0, h->variant, h->lcap), triplet_lds_bytes<P>(2, h->variant, h->lcap)) >
+        lds_limit())
+      return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) +
+                                    " neighbours needs more LDS per workgroup than the device allows");
     ta.G = G;
     launch_triplet<P>(0, h->variant, ta, stream);
     mk.mark("sf");
@@ -551,12 +560,9 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
     launch_wgrad<P>(wa, stream);
     mk.mark("wgrad");
     if ((st = check_launch(h, "backward"))) return st;
-    const int r = check_flags(h, stream, cm, &st);
-    if (r < 0) return st;
-    if (r == 0) {
-      mk.finish();
-      return NNP_OK;
-    }
+    NNP_HIP(h, hipStreamSynchronize(stream));
+    mk.finish();
+    return NNP_OK;
   }
   return fail(h, NNP_E_STATE, "neighbour capacity did not converge");
 }
@@ -760,15 +766,17 @@ nnp_status nnp_count_work(nnp_handle* h, int64_t n_atoms, const void* pos, const
   }
   unsigned long long* d_cnt;
   if ((st = ensure_t(h, "counts", 8, &d_cnt))) return st;
-  for (int attempt = 0; attempt < 8; ++attempt) {
+  bool built = false;
+  for (int attempt = 0; attempt < 8 && !built; ++attempt) {
     if ((st = build_neighbors(h, cm, s))) return st;
-    launch_fill_int(reinterpret_cast<int*>(d_cnt), 16, 0, s);
-    launch_count_terms(cm.bin, cm.nbr, cm.nnb, h->cap, ct, h->rc, d_cnt, s);
-    if ((st = check_launch(h, "count"))) return st;
     const int r = check_flags(h, s, cm, &st);
     if (r < 0) return st;
-    if (r == 0) break;
+    built = r == 0;
   }
+  if (!built) return fail(h, NNP_E_STATE, "neighbour capacity did not converge");
+  launch_fill_int(reinterpret_cast<int*>(d_cnt), 16, 0, s);
+  launch_count_terms(cm.bin, cm.nbr, cm.nnb, h->cap, ct, h->rc, d_cnt, s);
+  if ((st = check_launch(h, "count"))) return st;
   unsigned long long c[8];
   NNP_HIP(h, hipMemcpy(c, d_cnt, sizeof(c), hipMemcpyDeviceToHost));
   for (int i = 0; i < 5; ++i) counts[i] = (int64_t)c[i];

@@ -17,7 +17,7 @@ constexpr int HID = 32;                              // padded hidden width and 
 constexpr int LD = 32;                               // row stride of G, dE/dG and JVP rows
 constexpr int FC_DEG_MAX = 16;                       // storage bound of the cutoff polynomial
 constexpr int WAVE = 64;
-constexpr int QCAP = 128;                            // per-wave triplet queue (ring)
+constexpr int QCAP = 128;                            // per-wave triplet queue (stack of pairs)
 
 enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2 };
 

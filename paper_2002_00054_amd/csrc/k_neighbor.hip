@@ -139,16 +139,10 @@ __global__ void k_element_offsets(int n_el, int total_cells, const int* __restri
   if (f <= n_el) eoff[f] = start[f * total_cells];
 }
 
-// Full neighbour list of every sorted atom, one thread per atom.  Writes at
-// most cap entries per row; the number found beyond cap is reported through
-// flags[1] (maximum count) so the caller can grow cap and rebuild.
-__global__ void __launch_bounds__(256) k_neighbors(int64_t n, const double4* __restrict__ pos4,
-                                                   const DevStruct* __restrict__ st, const int* __restrict__ start,
-                                                   int n_el, int total_cells, double rc2, int cap,
-                                                   int* __restrict__ nbr, int4* __restrict__ nnb,
-                                                   int* __restrict__ flags) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
+// Neighbours of sorted atom s within rc (see k_neighbors); returns the count.
+__device__ int neighbors_of(int64_t s, const double4* __restrict__ pos4, const DevStruct* __restrict__ st,
+                            const int* __restrict__ start, int n_el, int total_cells, double rc2, int cap,
+                            int* __restrict__ nbr, int4* __restrict__ nnb, int* __restrict__ flags) {
   const double4 p = pos4[s];
   const int b = struct_of(p.w);
   const DevStruct& S = st[b];
@@ -195,6 +189,31 @@ __global__ void __launch_bounds__(256) k_neighbors(int64_t n, const double4* __r
   }
   nnb[s] = make_int4(cnt[0], cnt[1], cnt[2], cnt[3]);
   if (total > cap) atomicMax(&flags[1], total);
+  return total;
+}
+
+// Full neighbour list of every sorted atom, one thread per atom.  Writes at
+// most cap entries per row; the number found beyond cap is reported through
+// flags[1] (maximum count) so the caller can grow cap and rebuild.  flags[2]
+// receives the largest count of any atom (it sizes the pair kernels' LDS).
+__global__ void __launch_bounds__(256) k_neighbors(int64_t n, const double4* __restrict__ pos4,
+                                                   const DevStruct* __restrict__ st, const int* __restrict__ start,
+                                                   int n_el, int total_cells, double rc2, int cap,
+                                                   int* __restrict__ nbr, int4* __restrict__ nnb,
+                                                   int* __restrict__ flags) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int total = 0;
+  if (s < n) total = neighbors_of(s, pos4, st, start, n_el, total_cells, rc2, cap, nbr, nnb, flags);
+  // block maximum of the counts, one atomic per block
+  __shared__ int bmax[4];
+  int w = total;
+  for (int o = 32; o > 0; o >>= 1) w = max(w, __shfl_xor(w, o));
+  if ((threadIdx.x & 63) == 0) bmax[threadIdx.x >> 6] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int b = max(max(bmax[0], bmax[1]), max(bmax[2], bmax[3]));
+    if (b > 0) atomicMax(&flags[2], b);
+  }
 }
 
 // Work counts of one evaluation, one thread per centre:

@@ -21,7 +21,7 @@ struct BinArgs {
   int* perm;                 // [n] sorted -> caller index
   double4* pos4;             // [n] sorted wrapped positions + ids
   int* eoff;                 // [n_el + 1] element offsets of the sorted order
-  int* flags;                // [0] bad type, [1] max neighbour count beyond cap
+  int* flags;                // [0] bad type, [1] max neighbour count beyond cap, [2] max count
 };
 
 void launch_fill_int(int* p, int64_t n, int v, hipStream_t stream);
@@ -43,7 +43,8 @@ struct TripArgs {
   using IO = typename Types<P>::IO;
   using FAcc = typename Types<P>::FAcc;
   int64_t n;                 // sorted atoms
-  int cap;                   // neighbour slots per atom
+  int cap;                   // neighbour slots per atom (row stride of nbr)
+  int lcap;                  // LDS capacity: >= the most neighbours of any atom
   const double4* pos4;
   const int* nbr;            // [n][cap]
   const int4* nnb;           // [n] neighbours per element block
@@ -59,7 +60,7 @@ struct TripArgs {
 template <int P>
 void launch_triplet(int mode, int ne, const TripArgs<P>& a, hipStream_t stream);
 template <int P>
-size_t triplet_lds_bytes(int mode, int ne, int cap);
+size_t triplet_lds_bytes(int mode, int ne, int lcap);
 
 // ---------------------------------------------------------------- K4/K8
 template <int P>
