@@ -304,7 +304,7 @@ struct Common {
   int64_t* d_chi = nullptr;
   int* d_sc = nullptr;
   BinArgs bin;
-  int* nbr = nullptr;
+  void* nbr = nullptr;   // [n][cap] Vec4<T> entries of the form's arithmetic type
   int4* nnb = nullptr;
 };
 
@@ -351,6 +351,7 @@ nnp_status prepare(nnp_handle* h, Common& cm, const IO* pos, const int32_t* type
   if ((st = ensure_t(h, "count", nkeys + 1, &a.count))) return st;
   if ((st = ensure_t(h, "start", nkeys + 1, &a.start))) return st;
   if ((st = ensure_t(h, "cursor", nkeys + 1, &a.cursor))) return st;
+  if ((st = ensure_t(h, "scan", nkeys / 4096 + 1, &a.scan))) return st;
   if ((st = ensure_t(h, "perm", std::max<int64_t>(n, 1), &a.perm))) return st;
   if ((st = ensure_t(h, "pos4", std::max<int64_t>(n, 1), &a.pos4))) return st;
   if ((st = ensure_t(h, "eoff", MAX_EL + 1, &a.eoff))) return st;
@@ -360,13 +361,19 @@ nnp_status prepare(nnp_handle* h, Common& cm, const IO* pos, const int32_t* type
   return NNP_OK;
 }
 
+template <class T>
 nnp_status build_neighbors(nnp_handle* h, Common& cm, hipStream_t stream) {
+  using E = typename Vec4<T>::type;
   nnp_status st;
   const int64_t n = std::max<int64_t>(cm.B.n, 1);
-  if ((st = ensure_t(h, "nbr", (size_t)n * h->cap, &cm.nbr))) return st;
+  E* nbr = nullptr;
+  int* cmax = nullptr;
+  if ((st = ensure_t(h, "nbr", (size_t)n * h->cap, &nbr))) return st;
   if ((st = ensure_t(h, "nnb", n, &cm.nnb))) return st;
+  if ((st = ensure_t(h, "cmax", std::max(cm.B.total_cells, 1), &cmax))) return st;
+  cm.nbr = nbr;
   launch_fill_int(cm.bin.flags + 1, 2, 0, stream);
-  launch_neighbors(cm.bin, h->rc, h->cap, cm.nbr, cm.nnb, stream);
+  launch_neighbors<T>(cm.bin, h->rc, h->cap, nbr, cm.nnb, cmax, stream);
   return NNP_OK;
 }
 
@@ -378,7 +385,7 @@ TripArgs<P> trip_args(nnp_handle* h, Common& cm) {
   t.cap = h->cap;
   t.lcap = h->lcap;
   t.pos4 = cm.bin.pos4;
-  t.nbr = cm.nbr;
+  t.nbr = reinterpret_cast<const typename Vec4<typename Types<P>::T>::type*>(cm.nbr);
   t.nnb = cm.nnb;
   t.st = cm.d_st;
   t.tab = reinterpret_cast<const DevTab<typename Types<P>::T>*>(h->d_tab);
@@ -439,7 +446,7 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
   if ((st = ensure_t(h, "partial", std::max<size_t>(cm.B.chunk_lo.size(), 1), &partial))) return st;
   if ((st = ensure_t(h, "energies", n_struct, &energies))) return st;
   for (int attempt = 0; attempt < 8; ++attempt) {
-    if ((st = build_neighbors(h, cm, stream))) return st;
+    if ((st = build_neighbors<T>(h, cm, stream))) return st;
     const int r = check_flags(h, stream, cm, &st);
     if (r < 0) return st;
     if (r > 0) continue;  // capacity grew: rebuild the neighbour list
@@ -519,7 +526,7 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
   if ((st = ensure_t(h, "wpart", (size_t)h->n_el * nch * NET_STRIDE, &part))) return st;
   if ((st = ensure_t(h, "wpad", (size_t)h->n_el * NET_STRIDE, &padded))) return st;
   for (int attempt = 0; attempt < 8; ++attempt) {
-    if ((st = build_neighbors(h, cm, stream))) return st;
+    if ((st = build_neighbors<T>(h, cm, stream))) return st;
     const int r = check_flags(h, stream, cm, &st);
     if (r < 0) return st;
     if (r > 0) continue;  // capacity grew: rebuild the neighbour list
@@ -768,14 +775,18 @@ nnp_status nnp_count_work(nnp_handle* h, int64_t n_atoms, const void* pos, const
   if ((st = ensure_t(h, "counts", 8, &d_cnt))) return st;
   bool built = false;
   for (int attempt = 0; attempt < 8 && !built; ++attempt) {
-    if ((st = build_neighbors(h, cm, s))) return st;
+    st = h->prec == NNP_FP64 ? build_neighbors<double>(h, cm, s) : build_neighbors<float>(h, cm, s);
+    if (st) return st;
     const int r = check_flags(h, s, cm, &st);
     if (r < 0) return st;
     built = r == 0;
   }
   if (!built) return fail(h, NNP_E_STATE, "neighbour capacity did not converge");
   launch_fill_int(reinterpret_cast<int*>(d_cnt), 16, 0, s);
-  launch_count_terms(cm.bin, cm.nbr, cm.nnb, h->cap, ct, h->rc, d_cnt, s);
+  if (h->prec == NNP_FP64)
+    launch_count_terms<double>(cm.bin, reinterpret_cast<const double4*>(cm.nbr), cm.nnb, h->cap, ct, h->rc, d_cnt, s);
+  else
+    launch_count_terms<float>(cm.bin, reinterpret_cast<const float4*>(cm.nbr), cm.nnb, h->cap, ct, h->rc, d_cnt, s);
   if ((st = check_launch(h, "count"))) return st;
   unsigned long long c[8];
   NNP_HIP(h, hipMemcpy(c, d_cnt, sizeof(c), hipMemcpyDeviceToHost));

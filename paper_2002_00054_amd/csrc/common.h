@@ -26,6 +26,21 @@ enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2 };
 //  Acc   per-atom SF neighbour sums
 //  FAcc  force accumulation
 //  IO    positions, per-atom energies and forces at the boundary; G~ and dE/dG rows
+// Four-vector of the arithmetic type.  Neighbour-list entries use it as
+// (dx, dy, dz, j): the minimum-image displacement r_j - r_i rounded once from
+// FP64 to T, and the neighbour's sorted index in the bits of w.
+template <class T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+__host__ __device__ inline int entry_index(const float4& e) { return __float_as_int(e.w); }
+__host__ __device__ inline int entry_index(const double4& e) { return (int)__double_as_longlong(e.w); }
+__device__ inline float4 make_entry(double dx, double dy, double dz, int j, float) {
+  return make_float4((float)dx, (float)dy, (float)dz, __int_as_float(j));
+}
+__device__ inline double4 make_entry(double dx, double dy, double dz, int j, double) {
+  return make_double4(dx, dy, dz, __longlong_as_double((long long)j));
+}
+
 template <int P> struct Types;
 template <> struct Types<P_FP64> { using T = double; using Acc = double; using FAcc = double; using IO = double; };
 template <> struct Types<P_FP32> { using T = float;  using Acc = float;  using FAcc = float;  using IO = float; };

@@ -60,30 +60,84 @@ __global__ void __launch_bounds__(256) k_bin(int64_t n, const TIn* __restrict__ 
 }
 
 // Exclusive scan of count[0, n) into start[0, n] (start[n] = total) and
-// cursor; one workgroup of 1024 threads, each owning a contiguous chunk.
-__global__ void __launch_bounds__(1024) k_scan(int n, const int* __restrict__ count, int* __restrict__ start,
-                                               int* __restrict__ cursor) {
-  __shared__ int sums[1024];
-  const int t = threadIdx.x;
-  const int chunk = (n + 1023) / 1024;
-  const int b = min(t * chunk, n), e = min(b + chunk, n);
-  int s = 0;
-  for (int i = b; i < e; ++i) s += count[i];
-  sums[t] = s;
+// cursor, in three passes: per-block sums of SCAN_PER keys, one block scanning
+// those sums, then each block scanning its keys from its offset.
+constexpr int SCAN_PER = 4096;  // keys per block (1024 threads x 4)
+
+// Exclusive scan of v over a 1024-thread block; *total receives the sum.
+__device__ inline int block_exclusive_scan(int v, int* sh, int* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wv] = x;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int v = t >= o ? sums[t - o] : 0;
-    __syncthreads();
-    sums[t] += v;
-    __syncthreads();
+  if (wv == 0) {
+    int y = lane < 16 ? sh[lane] : 0;
+    for (int o = 1; o < 16; o <<= 1) {
+      const int z = __shfl_up(y, o);
+      if (lane >= o) y += z;
+    }
+    if (lane < 16) sh[16 + lane] = y;
   }
-  int run = t ? sums[t - 1] : 0;
-  for (int i = b; i < e; ++i) {
-    start[i] = run;
-    cursor[i] = run;
-    run += count[i];
+  __syncthreads();
+  *total = sh[31];
+  const int r = (wv ? sh[15 + wv] : 0) + x - v;
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_sums(int n, const int* __restrict__ count, int* __restrict__ partial) {
+  __shared__ int sh[32];
+  const int base = blockIdx.x * SCAN_PER;
+  int v = 0;
+  for (int i = base + threadIdx.x; i < min(n, base + SCAN_PER); i += 1024) v += count[i];
+  int total;
+  (void)block_exclusive_scan(v, sh, &total);
+  if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// partial[b] <- exclusive prefix of the block sums; start[n] <- total.
+__global__ void __launch_bounds__(1024) k_scan_top(int nb, int n, int* __restrict__ partial, int* __restrict__ start) {
+  __shared__ int sh[32];
+  const int per = (nb + 1023) / 1024;
+  const int b0 = min((int)threadIdx.x * per, nb), b1 = min(b0 + per, nb);
+  int v = 0;
+  for (int b = b0; b < b1; ++b) v += partial[b];
+  int total;
+  int run = block_exclusive_scan(v, sh, &total);
+  for (int b = b0; b < b1; ++b) {
+    const int c = partial[b];
+    partial[b] = run;
+    run += c;
   }
-  if (t == 1023) start[n] = sums[1023];
+  if (threadIdx.x == 0) start[n] = total;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_apply(int n, const int* __restrict__ count,
+                                                     const int* __restrict__ partial, int* __restrict__ start,
+                                                     int* __restrict__ cursor) {
+  __shared__ int sh[32];
+  const int i0 = blockIdx.x * SCAN_PER + 4 * threadIdx.x;
+  int c[4];
+  int v = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    c[k] = i0 + k < n ? count[i0 + k] : 0;
+    v += c[k];
+  }
+  int total;
+  int run = partial[blockIdx.x] + block_exclusive_scan(v, sh, &total);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (i0 + k < n) {
+      start[i0 + k] = run;
+      cursor[i0 + k] = run;
+    }
+    run += c[k];
+  }
 }
 
 __global__ void __launch_bounds__(256) k_scatter(int64_t n, const int* __restrict__ key, int* __restrict__ cursor,
@@ -139,80 +193,207 @@ __global__ void k_element_offsets(int n_el, int total_cells, const int* __restri
   if (f <= n_el) eoff[f] = start[f * total_cells];
 }
 
-// Neighbours of sorted atom s within rc (see k_neighbors); returns the count.
-__device__ int neighbors_of(int64_t s, const double4* __restrict__ pos4, const DevStruct* __restrict__ st,
-                            const int* __restrict__ start, int n_el, int total_cells, double rc2, int cap,
-                            int* __restrict__ nbr, int4* __restrict__ nnb, int* __restrict__ flags) {
-  const double4 p = pos4[s];
-  const int b = struct_of(p.w);
-  const DevStruct& S = st[b];
-  const double L0 = S.L[0], L1 = S.L[1], L2 = S.L[2];
-  const double i0 = S.invL[0], i1 = S.invL[1], i2 = S.invL[2];
-  const int n0 = S.ncell[0], n1 = S.ncell[1], n2 = S.ncell[2];
-  const int c0 = cell_coord(p.x, i0, n0), c1 = cell_coord(p.y, i1, n1), c2 = cell_coord(p.z, i2, n2);
-  // Deduplicated stencil: three cells per axis if the axis has >= 3 cells,
-  // otherwise every cell of the axis once.
-  int cx[3], cy[3], cz[3];
-  const int mx = n0 >= 3 ? 3 : n0, my = n1 >= 3 ? 3 : n1, mz = n2 >= 3 ? 3 : n2;
-  for (int o = 0; o < 3; ++o) {
-    cx[o] = n0 >= 3 ? (c0 - 1 + o + n0) % n0 : o;
-    cy[o] = n1 >= 3 ? (c1 - 1 + o + n1) % n1 : o;
-    cz[o] = n2 >= 3 ? (c2 - 1 + o + n2) % n2 : o;
-  }
-  int* row = nbr + s * (int64_t)cap;
-  int total = 0;
-  int cnt[MAX_EL] = {0, 0, 0, 0};
+// Neighbour build, one workgroup per cell.  The candidates of the cell (all
+// atoms of the deduplicated 3x3x3 block of cells around it, element by
+// element) are staged in LDS in tiles; each wave then takes centres of the
+// cell in turn, tests 64 candidates per step in FP64 under the minimum image
+// and appends the passing ones to the centre's row with a ballot compaction,
+// so rows are written coalesced and grouped by neighbour element.  An entry
+// is (r_j - r_i rounded to T, j).  When every axis has >= 3 cells, the
+// staged candidates are shifted by the periodic image of their cell so the
+// displacement is a plain difference; otherwise the minimum image is taken
+// per pair.  At most cap entries are written per row; the largest count
+// beyond cap goes to flags[1] (the caller grows cap and rebuilds) and the
+// largest count of the cell to cmax[cell].
+constexpr int NB_TILE = 768;   // staged candidates per tile
+constexpr int NB_MAXC = 128;   // centres per batch (state kept in LDS across tiles)
+
+__device__ inline int centre_of(int ci, const int* cbeg, const int* clen, int n_el) {
   for (int f = 0; f < n_el; ++f) {
-    const int kb = f * total_cells + S.cellbase;
-    for (int ox = 0; ox < mx; ++ox)
-      for (int oy = 0; oy < my; ++oy)
-        for (int oz = 0; oz < mz; ++oz) {
-          const int k = kb + (cx[ox] * n1 + cy[oy]) * n2 + cz[oz];
-          const int tb = start[k], te = start[k + 1];
-          for (int t = tb; t < te; ++t) {
-            if (t == s) continue;
-            const double4 q = pos4[t];
-            double dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
-            dx -= L0 * rint(dx * i0);
-            dy -= L1 * rint(dy * i1);
-            dz -= L2 * rint(dz * i2);
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < rc2) {
-              if (total < cap) {
-                row[total] = t;
-                ++cnt[f];
-              }
-              ++total;
-            }
-          }
-        }
+    if (ci < clen[f]) return cbeg[f] + ci;
+    ci -= clen[f];
   }
-  nnb[s] = make_int4(cnt[0], cnt[1], cnt[2], cnt[3]);
-  if (total > cap) atomicMax(&flags[1], total);
-  return total;
+  return -1;
 }
 
-// Full neighbour list of every sorted atom, one thread per atom.  Writes at
-// most cap entries per row; the number found beyond cap is reported through
-// flags[1] (maximum count) so the caller can grow cap and rebuild.  flags[2]
-// receives the largest count of any atom (it sizes the pair kernels' LDS).
-__global__ void __launch_bounds__(256) k_neighbors(int64_t n, const double4* __restrict__ pos4,
-                                                   const DevStruct* __restrict__ st, const int* __restrict__ start,
-                                                   int n_el, int total_cells, double rc2, int cap,
-                                                   int* __restrict__ nbr, int4* __restrict__ nnb,
-                                                   int* __restrict__ flags) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int total = 0;
-  if (s < n) total = neighbors_of(s, pos4, st, start, n_el, total_cells, rc2, cap, nbr, nnb, flags);
-  // block maximum of the counts, one atomic per block
-  __shared__ int bmax[4];
-  int w = total;
-  for (int o = 32; o > 0; o >>= 1) w = max(w, __shfl_xor(w, o));
-  if ((threadIdx.x & 63) == 0) bmax[threadIdx.x >> 6] = w;
+template <class T>
+__global__ void __launch_bounds__(256) k_neighbors(const double4* __restrict__ pos4, const DevStruct* __restrict__ st,
+                                                   int n_struct, const int* __restrict__ start, int n_el,
+                                                   int total_cells, double rc2, int cap,
+                                                   typename Vec4<T>::type* __restrict__ nbr, int4* __restrict__ nnb,
+                                                   int* __restrict__ flags, int* __restrict__ cmax) {
+  __shared__ double4 sp[NB_TILE];
+  __shared__ int seg_first[MAX_EL * 27];
+  __shared__ int seg_off[MAX_EL * 27 + 1];
+  __shared__ double seg_shift[27][3];
+  __shared__ double4 cpos[NB_MAXC];
+  __shared__ int cidx[NB_MAXC];
+  __shared__ int c_tot[NB_MAXC];
+  __shared__ int c_bnd[NB_MAXC][MAX_EL];  // passing candidates before element f's block (-1: not reached)
+  __shared__ int red[4];
+  const int X = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int lo = 0, hi = n_struct - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (st[mid].cellbase <= X) lo = mid; else hi = mid - 1;
+  }
+  const DevStruct& S = st[lo];
+  const int n0 = S.ncell[0], n1 = S.ncell[1], n2 = S.ncell[2];
+  const int l = X - S.cellbase;
+  const int c0 = l / (n1 * n2), c1 = (l / n2) % n1, c2 = l % n2;
+  const bool shifted = n0 >= 3 && n1 >= 3 && n2 >= 3;
+  const int mx = n0 >= 3 ? 3 : n0, my = n1 >= 3 ? 3 : n1, mz = n2 >= 3 ? 3 : n2;
+  const int nst = mx * my * mz, nseg = n_el * nst;
+  int cbeg[MAX_EL], clen[MAX_EL], nc = 0;
+  for (int f = 0; f < MAX_EL; ++f) {
+    cbeg[f] = 0;
+    clen[f] = 0;
+    if (f < n_el) {
+      const int k = f * total_cells + X;
+      cbeg[f] = start[k];
+      clen[f] = start[k + 1] - cbeg[f];
+      nc += clen[f];
+    }
+  }
+  if (nc == 0) {
+    if (tid == 0) cmax[X] = 0;
+    return;
+  }
+  int len = 0;
+  if (tid < nseg) {
+    const int f = tid / nst, o = tid - f * nst;
+    const int ox = o / (my * mz), oy = (o / mz) % my, oz = o % mz;
+    const int cx = n0 >= 3 ? (c0 - 1 + ox + n0) % n0 : ox;
+    const int cy = n1 >= 3 ? (c1 - 1 + oy + n1) % n1 : oy;
+    const int cz = n2 >= 3 ? (c2 - 1 + oz + n2) % n2 : oz;
+    const int k = f * total_cells + S.cellbase + (cx * n1 + cy) * n2 + cz;
+    seg_first[tid] = start[k];
+    len = start[k + 1] - start[k];
+    if (f == 0) {
+      const int g[3] = {c0 - 1 + ox, c1 - 1 + oy, c2 - 1 + oz};
+      const int nn[3] = {n0, n1, n2};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) seg_shift[o][a] = !shifted ? 0.0 : (g[a] < 0 ? -S.L[a] : (g[a] >= nn[a] ? S.L[a] : 0.0));
+    }
+  }
+  // inclusive scan of the segment lengths (nseg <= 108: waves 0 and 1)
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int y = __shfl_up(len, o);
+    if (lane >= o) len += y;
+  }
+  if (lane == WAVE - 1) red[wv] = len;
+  __syncthreads();
+  if (wv == 1) len += red[0];
+  if (tid < nseg) seg_off[tid + 1] = len;
+  if (tid == 0) seg_off[0] = 0;
+  __syncthreads();
+  const int ntot = seg_off[nseg];
+  int ebeg[MAX_EL];  // first candidate index of each element
+  for (int f = 0; f < MAX_EL; ++f) ebeg[f] = f < n_el ? seg_off[f * nst] : ntot;
+  const double L0 = S.L[0], L1 = S.L[1], L2 = S.L[2];
+  const double i0 = S.invL[0], i1 = S.invL[1], i2 = S.invL[2];
+  int most = 0;
+  for (int cb = 0; cb < nc; cb += NB_MAXC) {
+    const int nbc = min(NB_MAXC, nc - cb);
+    for (int i = tid; i < nbc; i += 256) {
+      const int c = centre_of(cb + i, cbeg, clen, n_el);
+      cidx[i] = c;
+      cpos[i] = pos4[c];
+      c_tot[i] = 0;
+      for (int f = 0; f < MAX_EL; ++f) c_bnd[i][f] = f == 0 ? 0 : -1;
+    }
+    for (int t0 = 0; t0 < ntot; t0 += NB_TILE) {
+      const int tl = min(NB_TILE, ntot - t0);
+      __syncthreads();
+      for (int u = tid; u < tl; u += 256) {
+        const int g = t0 + u;
+        int a = 0, b = nseg - 1;
+        while (a < b) {
+          const int m = (a + b + 1) >> 1;
+          if (seg_off[m] <= g) a = m; else b = m - 1;
+        }
+        const int sidx = seg_first[a] + (g - seg_off[a]);
+        const int f = a / nst, o = a - f * nst;
+        double4 q = pos4[sidx];
+        q.x += seg_shift[o][0];
+        q.y += seg_shift[o][1];
+        q.z += seg_shift[o][2];
+        q.w = __longlong_as_double(((long long)f << 32) | (unsigned)sidx);
+        sp[u] = q;
+      }
+      __syncthreads();
+      for (int ci = wv; ci < nbc; ci += 4) {
+        const int c = cidx[ci];
+        const double4 p = cpos[ci];
+        int tot = c_tot[ci];
+        typename Vec4<T>::type* row = nbr + (int64_t)c * cap;
+        for (int u0 = 0; u0 < tl; u0 += WAVE) {
+          const int u = u0 + lane;
+          bool pass = false;
+          double dx = 0.0, dy = 0.0, dz = 0.0;
+          int sidx = 0;
+          if (u < tl) {
+            const double4 q = sp[u];
+            sidx = (int)(__double_as_longlong(q.w) & 0xffffffffll);
+            dx = q.x - p.x;
+            dy = q.y - p.y;
+            dz = q.z - p.z;
+            if (!shifted) {
+              dx -= L0 * rint(dx * i0);
+              dy -= L1 * rint(dy * i1);
+              dz -= L2 * rint(dz * i2);
+            }
+            pass = sidx != c && dx * dx + dy * dy + dz * dz < rc2;
+          }
+          const unsigned long long msk = __builtin_amdgcn_ballot_w64(pass);
+          const int rank = tot + lanes_below(msk);
+          const bool keep = pass && rank < cap;
+          if (keep) row[rank] = make_entry(dx, dy, dz, sidx, T(0));
+          // an element block starting inside this step: passing candidates before it
+          const int g0 = t0 + u0;
+          for (int e = 1; e < n_el; ++e) {
+            const int b = ebeg[e] - g0;
+            if (b >= 0 && b < WAVE && lane == 0)
+              c_bnd[ci][e] = tot + __popcll(msk & ((1ull << b) - 1ull));
+          }
+          tot += __popcll(msk);
+        }
+        if (lane == 0) c_tot[ci] = tot;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < nbc; i += 256) {
+      const int c = cidx[i];
+      const int tot = c_tot[i];
+      // rows hold the passing candidates in candidate order, clipped at cap
+      int kept[MAX_EL + 1];
+      for (int f = 0; f < MAX_EL; ++f) kept[f] = min(f < n_el && c_bnd[i][f] >= 0 ? c_bnd[i][f] : tot, cap);
+      kept[MAX_EL] = min(tot, cap);
+      nnb[c] = make_int4(kept[1] - kept[0], kept[2] - kept[1], kept[3] - kept[2], kept[4] - kept[3]);
+      if (tot > cap) atomicMax(&flags[1], tot);
+      most = max(most, tot);
+    }
+    __syncthreads();
+  }
+  for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
+  if (lane == 0) red[wv] = most;
+  __syncthreads();
+  if (tid == 0) cmax[X] = max(max(red[0], red[1]), max(red[2], red[3]));
+}
+
+// flags[2] = max over cells of cmax (one workgroup).
+__global__ void __launch_bounds__(1024) k_max_count(int ncells, const int* __restrict__ cmax, int* __restrict__ flags) {
+  __shared__ int red[16];
+  int m = 0;
+  for (int i = threadIdx.x; i < ncells; i += 1024) m = max(m, cmax[i]);
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int b = max(max(bmax[0], bmax[1]), max(bmax[2], bmax[3]));
-    if (b > 0) atomicMax(&flags[2], b);
+    for (int w = 1; w < 16; ++w) m = max(m, red[w]);
+    m = max(m, red[0]);
+    flags[2] = m;
   }
 }
 
@@ -224,21 +405,20 @@ __global__ void __launch_bounds__(256) k_neighbors(int64_t n, const double4* __r
 //   counts[3] angular SF-term updates (triplet terms x angular SFs of the class),
 //   counts[4] radial SF-term updates (neighbour entries x radial SFs of the
 //             centre / neighbour element pair).
+template <class E>
 __global__ void __launch_bounds__(256) k_count_terms(int64_t n, const double4* __restrict__ pos4,
-                                                     const DevStruct* __restrict__ st, const int* __restrict__ nbr,
-                                                     const int4* __restrict__ nnb, int cap, int n_el, CountTab ct,
-                                                     double rc2, unsigned long long* __restrict__ counts) {
+                                                     const E* __restrict__ nbr, const int4* __restrict__ nnb, int cap,
+                                                     int n_el, CountTab ct, double rc2,
+                                                     unsigned long long* __restrict__ counts) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
-  const double4 p = pos4[s];
-  const int e = elem_of(p.w);
-  const DevStruct& S = st[struct_of(p.w)];
+  const int e = elem_of(pos4[s].w);
   const int4 c4 = nnb[s];
   const int cnt[MAX_EL] = {c4.x, c4.y, c4.z, c4.w};
   int off[MAX_EL + 1];
   off[0] = 0;
   for (int f = 0; f < MAX_EL; ++f) off[f + 1] = off[f] + (f < n_el ? cnt[f] : 0);
-  const int* row = nbr + s * (int64_t)cap;
+  const E* row = nbr + s * (int64_t)cap;
   unsigned long long cand = 0, pass = 0, aterms = 0, rterms = 0;
   for (int f = 0; f < n_el; ++f) rterms += (unsigned long long)cnt[f] * ct.rad[e][f];
   for (int e1 = 0; e1 < n_el; ++e1)
@@ -247,19 +427,12 @@ __global__ void __launch_bounds__(256) k_count_terms(int64_t n, const double4* _
       if (na == 0) continue;
       unsigned long long pc = 0;
       for (int a = off[e1]; a < off[e1] + cnt[e1]; ++a) {
-        const double4 qa = pos4[row[a]];
-        double ax = qa.x - p.x, ay = qa.y - p.y, az = qa.z - p.z;
-        ax -= S.L[0] * rint(ax * S.invL[0]);
-        ay -= S.L[1] * rint(ay * S.invL[1]);
-        az -= S.L[2] * rint(az * S.invL[2]);
+        const E qa = row[a];
         const int b0 = e1 == e2 ? a + 1 : off[e2];
         for (int b = b0; b < off[e2] + cnt[e2]; ++b) {
-          const double4 qb = pos4[row[b]];
-          double bx = qb.x - p.x, by = qb.y - p.y, bz = qb.z - p.z;
-          bx -= S.L[0] * rint(bx * S.invL[0]);
-          by -= S.L[1] * rint(by * S.invL[1]);
-          bz -= S.L[2] * rint(bz * S.invL[2]);
-          const double wx = bx - ax, wy = by - ay, wz = bz - az;
+          const E qb = row[b];
+          const double wx = (double)qb.x - (double)qa.x, wy = (double)qb.y - (double)qa.y,
+                       wz = (double)qb.z - (double)qa.z;
           ++cand;
           if (wx * wx + wy * wy + wz * wz < rc2) ++pc;
         }
@@ -285,7 +458,10 @@ void launch_bin_sort(const BinArgs& a, const TIn* pos, hipStream_t stream) {
     hipLaunchKernelGGL(k_bin<TIn>, dim3(g), dim3(256), 0, stream, n, pos, a.types, a.st, a.soff, a.n_struct,
                        a.n_el, a.total_cells, a.key, a.count, a.flags);
   }
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, nkeys, a.count, a.start, a.cursor);
+  const int nb = (nkeys + SCAN_PER - 1) / SCAN_PER;
+  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(1024), 0, stream, nkeys, a.count, a.scan);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, stream, nb, nkeys, a.scan, a.start);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, stream, nkeys, a.count, a.scan, a.start, a.cursor);
   if (n > 0) {
     const unsigned g = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, stream, n, a.key, a.cursor, a.perm);
@@ -299,19 +475,28 @@ void launch_bin_sort(const BinArgs& a, const TIn* pos, hipStream_t stream) {
 template void launch_bin_sort<float>(const BinArgs&, const float*, hipStream_t);
 template void launch_bin_sort<double>(const BinArgs&, const double*, hipStream_t);
 
-void launch_neighbors(const BinArgs& a, double rc, int cap, int* nbr, int4* nnb, hipStream_t stream) {
+template <class T>
+void launch_neighbors(const BinArgs& a, double rc, int cap, typename Vec4<T>::type* nbr, int4* nnb, int* cmax,
+                      hipStream_t stream) {
   if (a.n == 0) return;
-  const unsigned g = (unsigned)((a.n + 255) / 256);
-  hipLaunchKernelGGL(k_neighbors, dim3(g), dim3(256), 0, stream, a.n, a.pos4, a.st, a.start, a.n_el,
-                     a.total_cells, rc * rc, cap, nbr, nnb, a.flags);
+  hipLaunchKernelGGL(k_neighbors<T>, dim3((unsigned)a.total_cells), dim3(256), 0, stream, a.pos4, a.st, a.n_struct,
+                     a.start, a.n_el, a.total_cells, rc * rc, cap, nbr, nnb, a.flags, cmax);
+  hipLaunchKernelGGL(k_max_count, dim3(1), dim3(1024), 0, stream, a.total_cells, cmax, a.flags);
 }
+template void launch_neighbors<float>(const BinArgs&, double, int, float4*, int4*, int*, hipStream_t);
+template void launch_neighbors<double>(const BinArgs&, double, int, double4*, int4*, int*, hipStream_t);
 
-void launch_count_terms(const BinArgs& a, const int* nbr, const int4* nnb, int cap, const CountTab& ct, double rc,
-                        unsigned long long* counts, hipStream_t stream) {
+template <class T>
+void launch_count_terms(const BinArgs& a, const typename Vec4<T>::type* nbr, const int4* nnb, int cap,
+                        const CountTab& ct, double rc, unsigned long long* counts, hipStream_t stream) {
   if (a.n == 0) return;
   const unsigned g = (unsigned)((a.n + 255) / 256);
-  hipLaunchKernelGGL(k_count_terms, dim3(g), dim3(256), 0, stream, a.n, a.pos4, a.st, nbr, nnb, cap, a.n_el, ct,
-                     rc * rc, counts);
+  hipLaunchKernelGGL(k_count_terms<typename Vec4<T>::type>, dim3(g), dim3(256), 0, stream, a.n, a.pos4, nbr, nnb,
+                     cap, a.n_el, ct, rc * rc, counts);
 }
+template void launch_count_terms<float>(const BinArgs&, const float4*, const int4*, int, const CountTab&, double,
+                                        unsigned long long*, hipStream_t);
+template void launch_count_terms<double>(const BinArgs&, const double4*, const int4*, int, const CountTab&, double,
+                                         unsigned long long*, hipStream_t);
 
 }  // namespace nnp

@@ -18,6 +18,7 @@ struct BinArgs {
   int* count;                // [n_el * total_cells + 1]
   int* start;                // [n_el * total_cells + 1]
   int* cursor;               // [n_el * total_cells + 1]
+  int* scan;                 // [ceil((n_el * total_cells) / 4096)] block sums of the scan
   int* perm;                 // [n] sorted -> caller index
   double4* pos4;             // [n] sorted wrapped positions + ids
   int* eoff;                 // [n_el + 1] element offsets of the sorted order
@@ -27,14 +28,18 @@ struct BinArgs {
 void launch_fill_int(int* p, int64_t n, int v, hipStream_t stream);
 template <class TIn>
 void launch_bin_sort(const BinArgs& a, const TIn* pos, hipStream_t stream);
-void launch_neighbors(const BinArgs& a, double rc, int cap, int* nbr, int4* nnb, hipStream_t stream);
+// Neighbour rows of (dx, dy, dz, j) entries; cmax: [total_cells] scratch.
+template <class T>
+void launch_neighbors(const BinArgs& a, double rc, int cap, typename Vec4<T>::type* nbr, int4* nnb, int* cmax,
+                      hipStream_t stream);
 // Angular / radial SF counts per (centre, class) and (centre, neighbour element).
 struct CountTab {
   int ang[MAX_EL][MAX_CLS];
   int rad[MAX_EL][MAX_EL];
 };
-void launch_count_terms(const BinArgs& a, const int* nbr, const int4* nnb, int cap, const CountTab& ct, double rc,
-                        unsigned long long* counts, hipStream_t stream);
+template <class T>
+void launch_count_terms(const BinArgs& a, const typename Vec4<T>::type* nbr, const int4* nnb, int cap,
+                        const CountTab& ct, double rc, unsigned long long* counts, hipStream_t stream);
 
 // ---------------------------------------------------------------- K3/K5/K7
 template <int P>
@@ -46,7 +51,7 @@ struct TripArgs {
   int cap;                   // neighbour slots per atom (row stride of nbr)
   int lcap;                  // LDS capacity: >= the most neighbours of any atom
   const double4* pos4;
-  const int* nbr;            // [n][cap]
+  const typename Vec4<T>::type* nbr;  // [n][cap] (dx, dy, dz, j) entries
   const int4* nnb;           // [n] neighbours per element block
   const DevStruct* st;
   const DevTab<T>* tab;
