@@ -3,7 +3,7 @@
 fc(t) = (1 + cos(pi sqrt(t))) / 2 on t = r^2 / rc^2 in [0, 1], interpolated at
 the Chebyshev points of degree 6 and converted to the monomial basis.  Max
 error 5.5e-9 in fc and 5.4e-7 in dfc/dt (FP32 rounding is 6e-8).  Prints the
-C++ initialiser pasted into common.h (FcCoef<float>).
+C++ initialiser pasted into common.h (FcPoly<float>).
 
     python paper_2002_00054_amd/csrc/gen_cutoff_fp32.py
 """
