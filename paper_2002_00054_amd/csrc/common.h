@@ -138,6 +138,35 @@ __device__ inline T wave_sum(T v) {
 
 __device__ inline int lane_id() { return __lane_id(); }
 
+// Sums K per-lane values over the wave, 8 at a time, and stores total v in
+// out[v] (from one lane each).  Three exchange-and-add halvings (lane ^ 32,
+// lane ^ 16, lane ^ 8) leave each lane one of the 8 values summed over 8
+// lanes; three row shifts finish the sum within each aligned group of 8.
+template <class T>
+__device__ inline T shfl_xor_t(T v, int m) { return __shfl_xor(v, m); }
+template <class Acc, int K>
+__device__ inline void wave_sum_many(const Acc (&x)[K], Acc* out, int lane) {
+  const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
+  const int vi = (h32 ? 4 : 0) + (h16 ? 2 : 0) + (h8 ? 1 : 0);
+#pragma unroll
+  for (int g0 = 0; g0 < K; g0 += 8) {
+    Acc v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = g0 + i < K ? x[g0 + i] : Acc(0);
+    Acc a[4], b[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = (h32 ? v[i + 4] : v[i]) + shfl_xor_t(h32 ? v[i] : v[i + 4], 32);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) b[i] = (h16 ? a[i + 2] : a[i]) + shfl_xor_t(h16 ? a[i] : a[i + 2], 16);
+    Acc c = (h8 ? b[1] : b[0]) + dpp_shift<0x128>(h8 ? b[0] : b[1]);  // row_ror:8 = lane ^ 8
+    c += dpp_shift<0x111>(c);                                          // row_shr:1
+    c += dpp_shift<0x112>(c);                                          // row_shr:2
+    c += dpp_shift<0x114>(c);                                          // row_shr:4
+    if ((lane & 7) == 7 && g0 + vi < K) out[g0 + vi] = c;
+  }
+}
+
+
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Number of set bits of mask below this lane.
@@ -232,6 +261,7 @@ __host__ __device__ constexpr int q_k(int q) { return q % 6; }
 __host__ __device__ constexpr int q_zeta(int q) { return 1 << (q % 6); }
 __host__ __device__ constexpr uint64_t qn_bit(int q, int n) { return 1ull << (q * MAX_NE + n); }
 __host__ __device__ constexpr bool qn_used(uint64_t mask, int q, int n) { return (mask >> (q * MAX_NE + n)) & 1ull; }
+__host__ __device__ constexpr int qn_count(uint64_t mask) { return mask ? (int)(mask & 1ull) + qn_count(mask >> 1) : 0; }
 __host__ __device__ constexpr bool q_used(uint64_t mask, int q) {
   return ((mask >> (q * MAX_NE)) & ((1ull << MAX_NE) - 1)) != 0;
 }

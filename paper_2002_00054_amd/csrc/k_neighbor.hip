@@ -205,8 +205,8 @@ __global__ void k_element_offsets(int n_el, int total_cells, const int* __restri
 // per pair.  At most cap entries are written per row; the largest count
 // beyond cap goes to flags[1] (the caller grows cap and rebuilds) and the
 // largest count of the cell to cmax[cell].
-constexpr int NB_TILE = 768;   // staged candidates per tile
-constexpr int NB_MAXC = 128;   // centres per batch (state kept in LDS across tiles)
+constexpr int NB_TILE = 512;   // staged candidates per tile
+constexpr int NB_MAXC = 64;    // centres per batch (state kept in LDS across tiles)
 
 __device__ inline int centre_of(int ci, const int* cbeg, const int* clen, int n_el) {
   for (int f = 0; f < n_el; ++f) {
