@@ -164,3 +164,45 @@ def test_batch_equals_single(pots):
         assert eb[k].item() == pytest.approx(e1, rel=1e-13)
         np.testing.assert_allclose(ei[offs[k]:offs[k + 1]].cpu().numpy(), ei1, rtol=1e-13, atol=1e-14)
         np.testing.assert_allclose(f[offs[k]:offs[k + 1]].cpu().numpy(), f1, rtol=1e-11, atol=1e-12)
+
+
+def test_count_work_matches_brute_force(pots):
+    """The work counts behind the roofline (nnp_count_work) against brute force
+    over the oracle's neighbour lists: entries, candidate pairs per class with
+    angular SFs, pairs with r_jk < rc, and the SF-term updates they imply."""
+    table, _ = water_potential()
+    b = synth.water_box(6, 3)
+    rc = 6.0
+    cnt, lst = oracle.neighbors(b.pos, b.box, rc)
+    ang = {}
+    rad = {}
+    for s in table:
+        if s.kind == 3:
+            key = (s.centre, min(s.nbr), max(s.nbr))
+            ang[key] = ang.get(key, 0) + 1
+        else:
+            key = (s.centre, s.nbr[0])
+            rad[key] = rad.get(key, 0) + 1
+    pairs = cand = trip = aterms = rterms = 0
+    for i in range(b.n_atoms):
+        ti = int(b.types[i])
+        nb = lst[i, :cnt[i]]
+        d = b.pos[nb] - b.pos[i]
+        d -= b.box * np.rint(d / b.box)
+        el = b.types[nb]
+        pairs += len(nb)
+        for f in (0, 1):
+            rterms += int(np.sum(el == f)) * rad.get((ti, f), 0)
+        table_na = np.array([[ang.get((ti, min(x, y), max(x, y)), 0) for y in (0, 1)] for x in (0, 1)])
+        A, C = np.triu_indices(len(nb), 1)
+        na = table_na[el[A], el[C]]
+        close = np.sum((d[A] - d[C]) ** 2, axis=1) < rc * rc
+        cand += int(np.sum(na > 0))
+        trip += int(np.sum((na > 0) & close))
+        aterms += int(np.sum(na[close]))
+    for prec in ("fp64", "fp32"):
+        pos, types = to_dev(b, pots[prec].dtype)
+        got = pots[prec].count_work(pos, types, b.box)
+        say(prec, "count_work", got)
+        assert got == {"pairs": pairs, "candidates": cand, "triplets": trip, "angular_terms": aterms,
+                       "radial_terms": rterms}
