@@ -405,46 +405,60 @@ __global__ void __launch_bounds__(1024) k_max_count(int ncells, const int* __res
 //   counts[3] angular SF-term updates (triplet terms x angular SFs of the class),
 //   counts[4] radial SF-term updates (neighbour entries x radial SFs of the
 //             centre / neighbour element pair).
+// One wave per centre (grid-stride): lanes own the j of a class block, the
+// k run as a uniform loop (one broadcast read per k).  Partial counts stay in
+// registers and are reduced once per wave.
 template <class E>
 __global__ void __launch_bounds__(256) k_count_terms(int64_t n, const double4* __restrict__ pos4,
                                                      const E* __restrict__ nbr, const int4* __restrict__ nnb, int cap,
                                                      int n_el, CountTab ct, double rc2,
                                                      unsigned long long* __restrict__ counts) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const int e = elem_of(pos4[s].w);
-  const int4 c4 = nnb[s];
-  const int cnt[MAX_EL] = {c4.x, c4.y, c4.z, c4.w};
-  int off[MAX_EL + 1];
-  off[0] = 0;
-  for (int f = 0; f < MAX_EL; ++f) off[f + 1] = off[f] + (f < n_el ? cnt[f] : 0);
-  const E* row = nbr + s * (int64_t)cap;
-  unsigned long long cand = 0, pass = 0, aterms = 0, rterms = 0;
-  for (int f = 0; f < n_el; ++f) rterms += (unsigned long long)cnt[f] * ct.rad[e][f];
-  for (int e1 = 0; e1 < n_el; ++e1)
-    for (int e2 = e1; e2 < n_el; ++e2) {
-      const int na = ct.ang[e][class_index(e1, e2, n_el)];
-      if (na == 0) continue;
-      unsigned long long pc = 0;
-      for (int a = off[e1]; a < off[e1] + cnt[e1]; ++a) {
-        const E qa = row[a];
-        const int b0 = e1 == e2 ? a + 1 : off[e2];
-        for (int b = b0; b < off[e2] + cnt[e2]; ++b) {
-          const E qb = row[b];
-          const double wx = (double)qb.x - (double)qa.x, wy = (double)qb.y - (double)qa.y,
-                       wz = (double)qb.z - (double)qa.z;
-          ++cand;
-          if (wx * wx + wy * wy + wz * wz < rc2) ++pc;
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  unsigned long long cand = 0, pass = 0, aterms = 0, entries = 0, rterms = 0;
+  for (int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); s < n; s += nwaves) {
+    const int e = elem_of(pos4[s].w);
+    const int4 c4 = nnb[s];
+    const int cnt[MAX_EL] = {c4.x, c4.y, c4.z, c4.w};
+    int off[MAX_EL + 1];
+    off[0] = 0;
+    for (int f = 0; f < MAX_EL; ++f) off[f + 1] = off[f] + (f < n_el ? cnt[f] : 0);
+    if (lane == 0) {
+      entries += (unsigned long long)off[n_el];
+      for (int f = 0; f < n_el; ++f) rterms += (unsigned long long)cnt[f] * ct.rad[e][f];
+    }
+    const E* row = nbr + s * (int64_t)cap;
+    for (int e1 = 0; e1 < n_el; ++e1)
+      for (int e2 = e1; e2 < n_el; ++e2) {
+        const int na = ct.ang[e][class_index(e1, e2, n_el)];
+        if (na == 0) continue;
+        const bool same = e1 == e2;
+        const int end1 = off[e1] + cnt[e1], end2 = off[e2] + cnt[e2];
+        for (int a0 = off[e1]; a0 < end1; a0 += WAVE) {
+          const int a = a0 + lane;
+          const bool va = a < end1;
+          E qa = row[a0];
+          if (va) qa = row[a];
+          for (int b = same ? a0 + 1 : off[e2]; b < end2; ++b) {
+            const E qb = row[b];
+            if (va && (!same || b > a)) {
+              const double wx = (double)qb.x - (double)qa.x, wy = (double)qb.y - (double)qa.y,
+                           wz = (double)qb.z - (double)qa.z;
+              ++cand;
+              if (wx * wx + wy * wy + wz * wz < rc2) {
+                ++pass;
+                aterms += (unsigned long long)na;
+              }
+            }
+          }
         }
       }
-      pass += pc;
-      aterms += pc * (unsigned long long)na;
-    }
-  atomicAdd(&counts[0], (unsigned long long)off[n_el]);
-  atomicAdd(&counts[1], cand);
-  atomicAdd(&counts[2], pass);
-  atomicAdd(&counts[3], aterms);
-  atomicAdd(&counts[4], rterms);
+  }
+  unsigned long long v[5] = {entries, cand, pass, aterms, rterms};
+  for (int i = 0; i < 5; ++i) {
+    for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o);
+    if (lane == 0 && v[i]) atomicAdd(&counts[i], v[i]);
+  }
 }
 
 // ------------------------------------------------------------ launchers
@@ -490,7 +504,7 @@ template <class T>
 void launch_count_terms(const BinArgs& a, const typename Vec4<T>::type* nbr, const int4* nnb, int cap,
                         const CountTab& ct, double rc, unsigned long long* counts, hipStream_t stream) {
   if (a.n == 0) return;
-  const unsigned g = (unsigned)((a.n + 255) / 256);
+  const unsigned g = (unsigned)std::min<int64_t>((a.n + 3) / 4, 4096);
   hipLaunchKernelGGL(k_count_terms<typename Vec4<T>::type>, dim3(g), dim3(256), 0, stream, a.n, a.pos4, nbr, nnb,
                      cap, a.n_el, ct, rc * rc, counts);
 }
