@@ -183,24 +183,21 @@ __device__ inline float exp_scaled(float /*x_ln*/, float x_log2) { return __buil
 __device__ inline double rsqrt_t(double s) { return 1.0 / sqrt(s); }
 __device__ inline float rsqrt_t(float s) { return __builtin_amdgcn_rsqf(s); }
 
-// Coefficient a_n of fc = (1 + cos(pi sqrt(t)))/2 = sum_n a_n t^n, t = r^2/rc^2:
-// a_0 = 1, a_n = (-1)^n pi^(2n) / (2 (2n)!) for n >= 1 (Taylor series).
-__host__ __device__ constexpr double fc_taylor(int n) {
-  if (n == 0) return 1.0;
-  double a = 0.5;
-  const double pi2 = 9.8696044010893586188;  // pi^2
-  for (int k = 1; k <= n; ++k) a *= -pi2 / ((2.0 * k - 1.0) * (2.0 * k));
-  return a;
-}
-
-// Cutoff polynomial in t per arithmetic type.  FP64: Taylor series to degree
-// 14 (first omitted term < 2e-18 on [0, 1]).  FP32: degree-6 interpolant at
-// the Chebyshev points (gen_cutoff_fp32.py; max error 5.5e-9, below FP32
-// rounding), three terms shorter than the equivalent Taylor series.
+// Cutoff polynomial in t = r^2/rc^2 per arithmetic type: interpolants of
+// fc = (1 + cos(pi sqrt(t)))/2 at the Chebyshev points, in the monomial basis
+// (gen_cutoff.py).  FP64: degree 10, max error 1.4e-15 (fc) and 1.7e-13
+// (dfc/dt).  FP32: degree 6, max error 5.5e-9, below FP32 rounding.  Both are
+// several terms shorter than the Taylor series of the same accuracy.
 template <class T> struct FcPoly;
 template <> struct FcPoly<double> {
-  static constexpr int D = 14;
-  static constexpr double a(int n) { return fc_taylor(n); }
+  static constexpr int D = 10;
+  static constexpr double a(int n) {
+    constexpr double c[11] = {0.99999999999999867,    -2.4674011002721739,    2.0293560632041152,
+                              -0.66763138438064717,   0.11766531490754019,    -0.012903444753172158,
+                              0.00096478511035206918, -5.2316220181516193e-05, 2.1490610761661228e-06,
+                              -6.8101185620021584e-08, 1.44427758641541e-09};
+    return c[n];
+  }
 };
 template <> struct FcPoly<float> {
   static constexpr int D = 6;
