@@ -1,10 +1,11 @@
-"""Build the gfx950 HIP library ``libnnp.so`` in-tree with hipcc.
+"""Build the gfx950 HIP libraries in-tree with hipcc: ``libnnp.so`` (the
+energy+force path) and ``libnnp_peaks.so`` (the device peak probes).
 
     python -m paper_2002_00054_amd.build      (or __graft_entry__.build())
 
 Every source is compiled for gfx950 only, with packed FP32 instructions
 disabled (-Xclang -target-feature -Xclang -packed-fp32-ops), then linked into
-one shared library next to this file.
+the shared libraries next to this file.
 """
 from __future__ import annotations
 
@@ -19,6 +20,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnnp.so")
 SOURCES = ["api.hip", "k_neighbor.hip", "k_misc.hip", "k_mlp.hip",
            "k_triplet_f64.hip", "k_triplet_f32.hip", "k_triplet_bf16.hip"]
+PEAKS_LIB = os.path.join(HERE, "libnnp_peaks.so")
+PEAKS_SOURCES = ["peaks.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -35,19 +38,24 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
-    """Compile every source and link libnnp.so; returns its path."""
-    os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(lib: str, objs) -> None:
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = True) -> str:
+    """Compile every source and link both libraries; returns libnnp.so's path."""
+    os.makedirs(BUILD, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(_compile, SOURCES + PEAKS_SOURCES))
+    _link(LIB, objs[:len(SOURCES)])
+    _link(PEAKS_LIB, objs[len(SOURCES):])
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", PEAKS_LIB)
     return LIB
 
 

@@ -33,6 +33,33 @@ def test_header_symbols_are_exported():
         assert hasattr(L, name), name
 
 
+def test_peaks_header_symbols_are_exported():
+    from paper_2002_00054_amd import peaks
+
+    if not os.path.exists(peaks.LIB_PATH):
+        from paper_2002_00054_amd import build
+
+        build.build(verbose=False)
+    L = peaks.load_library()
+    hdr = open(os.path.join(ROOT, "include", "nnp_peaks.h")).read()
+    declared = set(re.findall(r"\b(nnp_[a-z0-9_]+)\s*\(", hdr))
+    assert declared == set(peaks.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_peaks_reject_bad_arguments():
+    """Argument errors come back as -1 before any launch (no GPU needed)."""
+    from paper_2002_00054_amd import peaks
+
+    L = peaks.load_library()
+    assert L.nnp_peak_fma_f32(None, 1, 1, None) == -1
+    assert L.nnp_peak_fma_f64(C.c_void_p(16), 0, 1, None) == -1
+    assert L.nnp_peak_exp_f32(C.c_void_p(16), 1, 0, None) == -1
+    assert L.nnp_peak_copy(C.c_void_p(16), C.c_void_p(32), 32, 1, None) == -1  # overlapping
+    assert L.nnp_peak_copy(C.c_void_p(16), C.c_void_p(4096), 8, 1, None) == -1  # not a multiple of 16
+
+
 def _create(table, nets, precision="fp64"):
     nnp, _ = _lib()
     return nnp.Potential(table, nets, precision=precision)

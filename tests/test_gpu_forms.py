@@ -8,12 +8,14 @@ FP64), and the parameter gradient of the energy+force loss from
 nnp_backward matches the FP64 oracle's gradient (FP64 to 1e-8, FP32 to 1e-4
 relative L2 per layer) and central differences of the GPU loss.
 """
+import json
+
 import numpy as np
 import pytest
 
 import oracle
 from common import oracle_water, water_potential
-from gpu_common import make_potential, oracle_input, run, say
+from gpu_common import check_fp32, check_fp64, make_potential, oracle_input, run, say
 from paper_2002_00054_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -32,6 +34,32 @@ def test_bf16_form_errors_vs_oracle():
         f"(mean |F| {np.mean(np.abs(ref['F'])):.3e})")
     assert rmse_f <= 5e-3
     assert np.max(np.abs(de)) <= 5e-2
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16"])
+def test_accuracy_table_12288(form):
+    """Each form against the FP64 oracle on a 12,288-atom box (lattice side 16,
+    seed 12), printed as one JSON line: the accuracy column of the measured
+    results table.  Bars: FP64 1e-9 relative, FP32 1e-5 eV / 1e-4 eV/A,
+    BF16 force RMSE 5e-3 eV/A."""
+    b = synth.water_box(16, 12)
+    pot = make_potential(form)
+    e, ei, f = run(pot, b)
+    ref = oracle_water().compute(oracle_input(b, form), b.types, b.box, use_cells=True)
+    de, df = ei - ref["Ei"], f - ref["F"]
+    rmse_f = float(np.sqrt(np.mean(df ** 2)))
+    say(json.dumps({"report": "accuracy", "form": form, "atoms": b.n_atoms,
+                    "E_per_atom_abs_err": abs(e - ref["E"]) / b.n_atoms,
+                    "Ei_max_abs_err": float(np.max(np.abs(de))),
+                    "Ei_max_rel_err": float(np.max(np.abs(de) / np.maximum(np.abs(ref["Ei"]), 1e-300))),
+                    "F_max_abs_err": float(np.max(np.abs(df))), "F_rmse": rmse_f}))
+    if form == "fp64":
+        check_fp64(ei, f, ref["Ei"], ref["F"])
+    elif form == "fp32":
+        check_fp32(ei, f, ref["Ei"], ref["F"])
+    else:
+        assert rmse_f <= 5e-3
+    pot.close()
 
 
 def test_fp32_mfma_network_matches_oracle_tightly():
@@ -172,3 +200,28 @@ def test_position_gradient_of_forces_raises(train_setup):
     E, F = energy_forces(th, pos, pot, types, [0, b.n_atoms], b.box[None])
     with pytest.raises(NotImplementedError):
         torch.autograd.grad(F.sum(), pos)
+
+
+@pytest.fixture(scope="module")
+def full_batch():
+    """The 32-box training batch (192-1536 atoms per box, 30,108 atoms),
+    labelled by the teacher, with the oracle's loss gradient."""
+    table, nets = water_potential()
+    boxes = synth.training_batch()
+    Ehat, Fhat = oracle.batch_energy_forces(oracle.Potential(table, synth.teacher_nets()), boxes)
+    L, g = oracle.loss_and_grad(oracle.Potential(table, nets), boxes, Ehat, Fhat)
+    return dict(boxes=boxes, Ehat=Ehat, Fhat=Fhat, L=L, g=g, params=synth.flat_params(nets))
+
+
+@pytest.mark.parametrize("form,tol", [("fp64", 1e-8), ("fp32", 1e-4)])
+def test_weight_gradient_full_training_batch(full_batch, form, tol):
+    s = full_batch
+    pot = make_potential(form)
+    L, g = _gpu_loss_and_grad(pot, s["boxes"], s["Ehat"], s["Fhat"], s["params"])
+    rel = float(np.linalg.norm(g - s["g"]) / np.linalg.norm(s["g"]))
+    say(json.dumps({"report": "training_gradient", "form": form, "boxes": len(s["boxes"]),
+                    "atoms": int(sum(b.n_atoms for b in s["boxes"])), "loss_rel_err": abs(L - s["L"]) / s["L"],
+                    "grad_rel_l2_vs_oracle": rel}))
+    assert rel < tol
+    assert L == pytest.approx(s["L"], rel=tol)
+    pot.close()
