@@ -100,7 +100,8 @@ def report(table, nets):
     """Extra JSON lines instead of the contract line: the measured device peaks,
     every form over the size sweep, the training step of the differentiation
     form (32 uneven boxes, loss = energy MSE + 0.1 force MSE, synthetic
-    targets), and the CPU oracle on one thread and on all threads."""
+    targets) with recomputed and with stored SF derivatives, the forward with
+    each, and the CPU oracle on one thread and on all threads."""
     import numpy as np
     import torch
 
@@ -129,8 +130,9 @@ def report(table, nets):
     N = torch.tensor([bx.n_atoms for bx in boxes], dtype=torch.float64, device=dev)
     Eh = torch.tensor(rng.normal(-1.5, 0.1, len(boxes)) * N.cpu().numpy(), dtype=torch.float64, device=dev)
     Fhat = rng.normal(0.0, 1.0, (int(offs[-1]), 3))
-    for form in ("fp32", "fp64"):
+    for form, mode in (("fp32", "recompute"), ("fp32", "stored"), ("fp64", "recompute"), ("fp64", "stored")):
         pot = Potential(table, nets, precision=form)
+        pot.set_derivative_mode(mode)
         pos = torch.tensor(np.concatenate([bx.pos for bx in boxes]), dtype=pot.dtype, device=dev)
         t = torch.tensor(np.concatenate([bx.types for bx in boxes]), dtype=torch.int32, device=dev)
         Fh = torch.tensor(Fhat, dtype=pot.dtype, device=dev)
@@ -150,9 +152,24 @@ def report(table, nets):
             step()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / 5
-        print(json.dumps({"report": "training", "form": form, "boxes": len(boxes), "atoms": int(offs[-1]),
-                          "ms_per_step": dt * 1e3}), flush=True)
+        print(json.dumps({"report": "training", "form": form, "derivatives": mode, "boxes": len(boxes),
+                          "atoms": int(offs[-1]), "ms_per_step": dt * 1e3,
+                          "workspace_gb": pot.workspace_bytes / 1e9}), flush=True)
         pot.close()
+        torch.cuda.empty_cache()
+    # one energy+force evaluation with the stored-Jacobian forward (one eighth of the 2M box)
+    bb = synth.water_box(44, 22)
+    for mode in ("recompute", "stored"):
+        pot = Potential(table, nets, precision="fp32")
+        pot.set_derivative_mode(mode)
+        x = torch.tensor(bb.pos, dtype=torch.float32, device=dev)
+        t = torch.tensor(bb.types, dtype=torch.int32, device=dev)
+        ms, st = time_form(pot, x, t, bb.box, 5, 2)
+        print(json.dumps({"report": "forward_derivatives", "form": "fp32", "derivatives": mode, "atoms": bb.n_atoms,
+                          "ms_per_step": ms, "stages_ms": st, "workspace_gb": pot.workspace_bytes / 1e9}),
+              flush=True)
+        pot.close()
+        del x, t
         torch.cuda.empty_cache()
     for nt in (0, 1):  # all threads first: a thread count set once stays set
         cb = cpu_baseline(table, nets, budget_s=30.0 if nt == 1 else 12.0, nthreads=nt)

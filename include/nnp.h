@@ -151,7 +151,8 @@ nnp_status nnp_compute_batch(nnp_handle* h, int n_struct, const int64_t* atom_of
  * every network parameter, given dL/dE_b and dL/dF of the batch evaluated by
  * nnp_compute_batch with the same arguments:
  *   dL/dtheta = sum_b dL/dE_b dE_b/dtheta + sum_m dL/dF_m . dF_m/dtheta.
- * The descriptor derivatives are recomputed, not stored.
+ * By default the descriptor derivatives are recomputed, not stored (see
+ * nnp_set_derivative_mode for the stored alternative).
  *  dL_dE        device double [n_struct] (may be NULL: no energy term)
  *  dL_dF        device [n_atoms][3] in the positions' type (may be NULL: no force term)
  *  grad_params  device double [nnp_n_params(h)], overwritten; flat layout of
@@ -160,6 +161,31 @@ nnp_status nnp_compute_batch(nnp_handle* h, int n_struct, const int64_t* atom_of
 nnp_status nnp_backward(nnp_handle* h, int n_struct, const int64_t* atom_offsets, const void* pos,
                         const int32_t* types, const double* boxes, const double* dL_dE,
                         const void* dL_dF, void* grad_params, void* stream);
+
+/*
+ * How the differentiation form obtains the SF derivatives dG_is/dr_m.
+ *  NNP_DERIV_RECOMPUTE  (default) the force pass and nnp_backward recompute
+ *                       them from the neighbour list, as the paper does
+ *                       (Sec. 3.3): nothing per pair or triplet is kept.
+ *  NNP_DERIV_STORED     every forward evaluation also stores, for each centre
+ *                       i, neighbour slot and SF s, the gradient dG_is/dr_j
+ *                       (3 * max n_sf * n_atoms * capacity values of the
+ *                       positions' type in the handle's workspace); forces are
+ *                       a contraction of that store, and nnp_backward with the
+ *                       same inputs as the last forward reuses it instead of
+ *                       rebuilding the neighbour list and SFs.  Whether the
+ *                       inputs are the same is checked (batch layout on the
+ *                       host, positions and types bitwise on the device);
+ *                       otherwise nnp_backward recomputes the store first.
+ * NNP_DERIV_STORED needs an NNP_FP64 or NNP_FP32 handle (NNP_E_STATE
+ * otherwise); an unknown mode is NNP_E_ARG.  Takes effect at the next call.
+ */
+typedef enum { NNP_DERIV_RECOMPUTE = 0, NNP_DERIV_STORED = 1 } nnp_deriv_mode;
+nnp_status nnp_set_derivative_mode(nnp_handle* h, int mode);
+
+/* Device memory held by the handle's workspace, in bytes (grow-only buffers
+ * kept until nnp_destroy; excludes the parameter and table blocks). */
+int64_t nnp_workspace_bytes(const nnp_handle* h);
 
 /* Number of network parameters: sum over elements and layers of out*in + out. */
 int64_t nnp_n_params(const nnp_handle* h);

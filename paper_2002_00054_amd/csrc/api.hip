@@ -57,6 +57,13 @@ struct nnp_handle {
   std::vector<double> t_ms;
   std::vector<hipEvent_t> events;
   bool has_forward = false;
+  // stored-Jacobian differentiation form: the last forward's inputs, for
+  // reuse of its J store by nnp_backward
+  int deriv_mode = NNP_DERIV_RECOMPUTE;
+  bool jac_valid = false;
+  int jac_cap = 0;
+  std::vector<int64_t> jac_offs;
+  std::vector<double> jac_boxes;
 };
 
 namespace nnp {
@@ -309,8 +316,11 @@ struct Common {
 };
 
 // Uploads the batch description and runs wrap + bin + counting sort.
+// With sort = false the buffers are only bound (their contents are those of
+// the last sorted batch) and nothing is launched.
 template <class IO>
-nnp_status prepare(nnp_handle* h, Common& cm, const IO* pos, const int32_t* types, hipStream_t stream) {
+nnp_status prepare(nnp_handle* h, Common& cm, const IO* pos, const int32_t* types, hipStream_t stream,
+                   bool sort = true) {
   Batch& B = cm.B;
   const int64_t n = B.n;
   const int nkeys = h->n_el * B.total_cells;
@@ -356,8 +366,22 @@ nnp_status prepare(nnp_handle* h, Common& cm, const IO* pos, const int32_t* type
   if ((st = ensure_t(h, "pos4", std::max<int64_t>(n, 1), &a.pos4))) return st;
   if ((st = ensure_t(h, "eoff", MAX_EL + 1, &a.eoff))) return st;
   if ((st = ensure_t(h, "flags", 4, &a.flags))) return st;
+  if (!sort) return NNP_OK;
+  h->jac_valid = false;  // the sorted order, neighbour list and J store are about to change
   launch_fill_int(a.flags, 4, 0, stream);
   launch_bin_sort<IO>(a, pos, stream);
+  return NNP_OK;
+}
+
+template <class T>
+nnp_status bind_neighbors(nnp_handle* h, Common& cm) {
+  using E = typename Vec4<T>::type;
+  nnp_status st;
+  const int64_t n = std::max<int64_t>(cm.B.n, 1);
+  E* nbr = nullptr;
+  if ((st = ensure_t(h, "nbr", (size_t)n * h->cap, &nbr))) return st;
+  if ((st = ensure_t(h, "nnb", n, &cm.nnb))) return st;
+  cm.nbr = nbr;
   return NNP_OK;
 }
 
@@ -416,6 +440,80 @@ int check_flags(nnp_handle* h, hipStream_t stream, Common& cm, nnp_status* st) {
   return 0;
 }
 
+// The stored-Jacobian form applies to the FP64 and FP32 handles.
+template <int P>
+bool stored_jacobian(const nnp_handle* h) {
+  return P != P_BF16 && h->deriv_mode == NNP_DERIV_STORED;
+}
+
+template <int P>
+nnp_status jac_setup(nnp_handle* h, Common& cm, JacArgs<P>& j) {
+  using T = typename Types<P>::T;
+  std::memset(&j, 0, sizeof(j));
+  int ns_max = 1;
+  for (int e = 0; e < h->n_el; ++e) ns_max = std::max(ns_max, h->n_sf[e]);
+  const int64_t n1 = std::max<int64_t>(cm.B.n, 1);
+  j.n = cm.B.n;
+  j.cap = h->cap;
+  j.lcap = h->lcap;
+  j.nbr = reinterpret_cast<const typename Vec4<T>::type*>(cm.nbr);
+  j.nnb = cm.nnb;
+  j.pos4 = cm.bin.pos4;
+  j.tab = reinterpret_cast<const DevTab<T>*>(h->d_tab);
+  j.plane = n1 * h->cap;
+  return ensure_t(h, "J", (size_t)3 * ns_max * j.plane, &j.J);
+}
+
+// Keeps a copy of the inputs whose J store is now in the workspace.
+template <class IO>
+nnp_status jac_remember(nnp_handle* h, const Common& cm, const IO* pos, const int32_t* types, hipStream_t stream) {
+  const int64_t n = cm.B.n;
+  IO* sp;
+  int32_t* stp;
+  nnp_status st;
+  if ((st = ensure_t(h, "jpos", (size_t)std::max<int64_t>(n, 1) * 3, &sp))) return st;
+  if ((st = ensure_t(h, "jtypes", (size_t)std::max<int64_t>(n, 1), &stp))) return st;
+  if (n > 0) {
+    NNP_HIP(h, hipMemcpyAsync(sp, pos, (size_t)n * 3 * sizeof(IO), hipMemcpyDeviceToDevice, stream));
+    NNP_HIP(h, hipMemcpyAsync(stp, types, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
+  }
+  h->jac_offs.assign(cm.B.soff.begin(), cm.B.soff.end());
+  h->jac_boxes.clear();
+  for (const auto& d : cm.B.st) h->jac_boxes.insert(h->jac_boxes.end(), d.L, d.L + 3);
+  h->jac_cap = h->cap;
+  return NNP_OK;
+}
+
+// True if the workspace still holds the J store of exactly these inputs
+// (same batch layout, same capacity, bitwise equal positions and types).
+// Binds the sorted-order buffers of cm either way.
+template <class IO>
+bool jac_reusable(nnp_handle* h, Common& cm, const IO* pos, const int32_t* types, hipStream_t stream,
+                  nnp_status* st) {
+  *st = NNP_OK;
+  if (!h->jac_valid || h->jac_cap != h->cap) return false;
+  if (h->jac_offs.size() != cm.B.soff.size() ||
+      !std::equal(h->jac_offs.begin(), h->jac_offs.end(), cm.B.soff.begin()))
+    return false;
+  std::vector<double> boxes;
+  for (const auto& d : cm.B.st) boxes.insert(boxes.end(), d.L, d.L + 3);
+  if (boxes != h->jac_boxes) return false;
+  IO* sp;
+  int32_t* stp;
+  if ((*st = ensure_t(h, "jpos", (size_t)std::max<int64_t>(cm.B.n, 1) * 3, &sp))) return false;
+  if ((*st = ensure_t(h, "jtypes", (size_t)std::max<int64_t>(cm.B.n, 1), &stp))) return false;
+  if ((*st = prepare<IO>(h, cm, pos, types, stream, false))) return false;
+  launch_fill_int(cm.bin.flags + 3, 1, 0, stream);
+  launch_same_inputs<IO>(cm.B.n, pos, sp, types, stp, cm.bin.flags + 3, stream);
+  hipError_t e = hipMemcpyAsync(h->h_flags + 3, cm.bin.flags + 3, sizeof(int), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    *st = fail(h, NNP_E_HIP, std::string("readback: ") + hipGetErrorString(e));
+    return false;
+  }
+  return h->h_flags[3] == 0;
+}
+
 template <int P>
 nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void* pos_v, const int32_t* types,
                    const double* boxes, double* energies_dev, double* energy_host, void* ei_v, void* f_v,
@@ -445,6 +543,7 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
   if ((st = ensure_t(h, "Ei_o", n1, &Ei_o))) return st;
   if ((st = ensure_t(h, "partial", std::max<size_t>(cm.B.chunk_lo.size(), 1), &partial))) return st;
   if ((st = ensure_t(h, "energies", n_struct, &energies))) return st;
+  const bool stored = stored_jacobian<P>(h);
   for (int attempt = 0; attempt < 8; ++attempt) {
     if ((st = build_neighbors<T>(h, cm, stream))) return st;
     const int r = check_flags(h, stream, cm, &st);
@@ -452,13 +551,6 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
     if (r > 0) continue;  // capacity grew: rebuild the neighbour list
     mk.mark("neighbors");
     TripArgs<P> ta = trip_args<P>(h, cm);
-    const size_t lds = std::max(triplet_lds_bytes<P>(0, h->variant, h->lcap), triplet_lds_bytes<P>(1, h->variant, h->lcap));
-    if (lds > lds_limit())
-      return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) + " neighbours needs " + std::to_string(lds) +
-                                    " bytes of LDS per workgroup, more than the device allows");
-    ta.G = G;
-    launch_triplet<P>(0, h->variant, ta, stream);
-    mk.mark("sf");
     MlpArgs<P> ma;
     std::memset(&ma, 0, sizeof(ma));
     ma.n = n;
@@ -469,13 +561,43 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
     ma.Ei = Ei_s;
     ma.nets = reinterpret_cast<const T*>(h->d_nets);
     ma.tab = ta.tab;
-    launch_fill<FAcc>(F_s, n * 3, FAcc(0), stream);
-    launch_mlp<P>(ma, stream);
-    mk.mark("mlp");
-    ta.C = C;
-    ta.F = F_s;
-    launch_triplet<P>(1, h->variant, ta, stream);
-    mk.mark("force");
+    if constexpr (P != P_BF16) {
+      if (stored) {
+        JacArgs<P> ja;
+        if ((st = jac_setup<P>(h, cm, ja))) return st;
+        if (jac_lds_bytes<P>(h->lcap) > lds_limit())
+          return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) +
+                                        " neighbours needs more LDS per workgroup than the device allows");
+        ja.G = G;
+        launch_jac<P>(ja, stream);
+        mk.mark("sf");
+        launch_fill<FAcc>(F_s, n * 3, FAcc(0), stream);
+        launch_mlp<P>(ma, stream);
+        mk.mark("mlp");
+        ja.C = C;
+        ja.F = F_s;
+        launch_jac_force<P>(ja, stream);
+        mk.mark("force");
+        if ((st = jac_remember<IO>(h, cm, pos, types, stream))) return st;
+      }
+    }
+    if (!stored) {
+      const size_t lds =
+          std::max(triplet_lds_bytes<P>(0, h->variant, h->lcap), triplet_lds_bytes<P>(1, h->variant, h->lcap));
+      if (lds > lds_limit())
+        return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) + " neighbours needs " +
+                                      std::to_string(lds) + " bytes of LDS per workgroup, more than the device allows");
+      ta.G = G;
+      launch_triplet<P>(0, h->variant, ta, stream);
+      mk.mark("sf");
+      launch_fill<FAcc>(F_s, n * 3, FAcc(0), stream);
+      launch_mlp<P>(ma, stream);
+      mk.mark("mlp");
+      ta.C = C;
+      ta.F = F_s;
+      launch_triplet<P>(1, h->variant, ta, stream);
+      mk.mark("force");
+    }
     launch_unpermute<IO, FAcc>(n, cm.bin.perm, Ei_s, F_s, Ei_o, reinterpret_cast<IO*>(ei_v),
                                reinterpret_cast<IO*>(f_v), stream);
     launch_energy(Ei_o, cm.d_clo, cm.d_chi, (int)cm.B.chunk_lo.size(), cm.d_sc, n_struct, partial, energies, stream);
@@ -489,6 +611,7 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
     if (energy_host) *energy_host = *h->h_energy;
     mk.finish();
     h->has_forward = true;
+    h->jac_valid = stored;
     return NNP_OK;
   }
   return fail(h, NNP_E_STATE, "neighbour capacity did not converge");
@@ -510,8 +633,6 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
   h->cap = initial_cap(h, cm.B);
   Marks mk(h, stream);
   (void)hipGetLastError();
-  if ((st = prepare<IO>(h, cm, pos, types, stream))) return st;
-  mk.mark("bin_sort");
   IO *G, *V, *delta;
   double *gE_atom, *part, *padded;
   T* vec;
@@ -525,53 +646,94 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
   if ((st = ensure_t(h, "wvec", (size_t)n1 * 11 * HID, &vec))) return st;
   if ((st = ensure_t(h, "wpart", (size_t)h->n_el * nch * NET_STRIDE, &part))) return st;
   if ((st = ensure_t(h, "wpad", (size_t)h->n_el * NET_STRIDE, &padded))) return st;
-  for (int attempt = 0; attempt < 8; ++attempt) {
+  const bool stored = stored_jacobian<P>(h);
+  bool ready = false;  // G and the J store (or the neighbour list) describe these inputs
+  if (stored) {
+    ready = jac_reusable<IO>(h, cm, pos, types, stream, &st);
+    if (st) return st;
+    if (ready && (st = bind_neighbors<T>(h, cm))) return st;
+    mk.mark(ready ? "reuse" : "compare");
+  }
+  if (!ready) {
+    if ((st = prepare<IO>(h, cm, pos, types, stream))) return st;
+    mk.mark("bin_sort");
+  }
+  for (int attempt = 0; attempt < 8 && !ready; ++attempt) {
     if ((st = build_neighbors<T>(h, cm, stream))) return st;
     const int r = check_flags(h, stream, cm, &st);
     if (r < 0) return st;
     if (r > 0) continue;  // capacity grew: rebuild the neighbour list
     mk.mark("neighbors");
+    if constexpr (P != P_BF16) {
+      if (stored) {
+        JacArgs<P> ja;
+        if ((st = jac_setup<P>(h, cm, ja))) return st;
+        if (jac_lds_bytes<P>(h->lcap) > lds_limit())
+          return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) +
+                                        " neighbours needs more LDS per workgroup than the device allows");
+        ja.G = G;
+        launch_jac<P>(ja, stream);
+        if ((st = jac_remember<IO>(h, cm, pos, types, stream))) return st;
+        mk.mark("sf");
+      }
+    }
+    if (!stored) {
+      TripArgs<P> ta = trip_args<P>(h, cm);
+      if (std::max(triplet_lds_bytes<P>(0, h->variant, h->lcap), triplet_lds_bytes<P>(2, h->variant, h->lcap)) >
+          lds_limit())
+        return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) +
+                                      " neighbours needs more LDS per workgroup than the device allows");
+      ta.G = G;
+      launch_triplet<P>(0, h->variant, ta, stream);
+      mk.mark("sf");
+    }
+    ready = true;
+  }
+  if (!ready) return fail(h, NNP_E_STATE, "neighbour capacity did not converge");
+  if (dLdF) launch_permute_rows3<IO>(n, cm.bin.perm, dLdF, delta, stream);
+  else launch_fill<IO>(delta, n * 3, IO(0), stream);
+  if constexpr (P != P_BF16) {
+    if (stored) {
+      JacArgs<P> ja;
+      if ((st = jac_setup<P>(h, cm, ja))) return st;
+      ja.delta = delta;
+      ja.V = V;
+      launch_jac_jvp<P>(ja, stream);
+    }
+  }
+  if (!stored) {
     TripArgs<P> ta = trip_args<P>(h, cm);
-    if (std::max(triplet_lds_bytes<P>(0, h->variant, h->lcap), triplet_lds_bytes<P>(2, h->variant, h->lcap)) >
-        lds_limit())
-      return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) +
-                                    " neighbours needs more LDS per workgroup than the device allows");
-    ta.G = G;
-    launch_triplet<P>(0, h->variant, ta, stream);
-    mk.mark("sf");
-    if (dLdF) launch_permute_rows3<IO>(n, cm.bin.perm, dLdF, delta, stream);
-    else launch_fill<IO>(delta, n * 3, IO(0), stream);
     ta.delta = delta;
     ta.V = V;
     launch_triplet<P>(2, h->variant, ta, stream);
-    mk.mark("jvp");
-    launch_gather_struct_grad(n, cm.bin.perm, cm.d_soff, n_struct, dL_dE, gE_atom, stream);
-    WGradArgs<P> wa;
-    std::memset(&wa, 0, sizeof(wa));
-    wa.n = n;
-    wa.n_el = h->n_el;
-    wa.eoff = cm.bin.eoff;
-    wa.G = G;
-    wa.V = V;
-    wa.gE_atom = gE_atom;
-    wa.nets = reinterpret_cast<const T*>(h->d_nets);
-    wa.tab = ta.tab;
-    wa.vec = vec;
-    wa.chunk = chunk;
-    wa.nch = nch;
-    wa.partial = part;
-    wa.padded = padded;
-    wa.n_params = (int64_t)h->params.size();
-    wa.flatmap = h->d_flatmap;
-    wa.out = grad;
-    launch_wgrad<P>(wa, stream);
-    mk.mark("wgrad");
-    if ((st = check_launch(h, "backward"))) return st;
-    NNP_HIP(h, hipStreamSynchronize(stream));
-    mk.finish();
-    return NNP_OK;
   }
-  return fail(h, NNP_E_STATE, "neighbour capacity did not converge");
+  mk.mark("jvp");
+  launch_gather_struct_grad(n, cm.bin.perm, cm.d_soff, n_struct, dL_dE, gE_atom, stream);
+  WGradArgs<P> wa;
+  std::memset(&wa, 0, sizeof(wa));
+  wa.n = n;
+  wa.n_el = h->n_el;
+  wa.eoff = cm.bin.eoff;
+  wa.G = G;
+  wa.V = V;
+  wa.gE_atom = gE_atom;
+  wa.nets = reinterpret_cast<const T*>(h->d_nets);
+  wa.tab = reinterpret_cast<const DevTab<T>*>(h->d_tab);
+  wa.vec = vec;
+  wa.chunk = chunk;
+  wa.nch = nch;
+  wa.partial = part;
+  wa.padded = padded;
+  wa.n_params = (int64_t)h->params.size();
+  wa.flatmap = h->d_flatmap;
+  wa.out = grad;
+  launch_wgrad<P>(wa, stream);
+  mk.mark("wgrad");
+  if ((st = check_launch(h, "backward"))) return st;
+  NNP_HIP(h, hipStreamSynchronize(stream));
+  mk.finish();
+  h->jac_valid = stored;
+  return NNP_OK;
 }
 
 // --------------------------------------------------------------- create
@@ -880,6 +1042,25 @@ int nnp_last_timings(const nnp_handle* h, const char** names, double* ms, int ma
   return k;
 }
 
+nnp_status nnp_set_derivative_mode(nnp_handle* h, int mode) {
+  if (!h) return NNP_E_ARG;
+  h->err.clear();
+  if (mode != NNP_DERIV_RECOMPUTE && mode != NNP_DERIV_STORED)
+    return fail(h, NNP_E_ARG, "derivative mode must be NNP_DERIV_RECOMPUTE or NNP_DERIV_STORED");
+  if (mode == NNP_DERIV_STORED && h->prec == NNP_BF16_MIXED)
+    return fail(h, NNP_E_STATE, "the stored-Jacobian mode needs an NNP_FP64 or NNP_FP32 handle");
+  if (mode != h->deriv_mode) h->jac_valid = false;
+  h->deriv_mode = mode;
+  return NNP_OK;
+}
+
+int64_t nnp_workspace_bytes(const nnp_handle* h) {
+  if (!h) return 0;
+  int64_t b = 0;
+  for (const auto& kv : h->ws) b += (int64_t)kv.second.bytes;
+  return b;
+}
+
 int nnp_neighbor_capacity(const nnp_handle* h) { return h ? h->cap : 0; }
 
 nnp_status nnp_set_neighbor_capacity(nnp_handle* h, int cap) {
@@ -887,6 +1068,7 @@ nnp_status nnp_set_neighbor_capacity(nnp_handle* h, int cap) {
   if (cap < 8) return fail(h, NNP_E_ARG, "capacity must be >= 8");
   h->cap_override = cap;
   h->cap = cap;
+  h->jac_valid = false;
   return NNP_OK;
 }
 

@@ -169,6 +169,17 @@ __device__ inline void wave_sum_many(const Acc (&x)[K], Acc* out, int lane) {
 
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Workgroup index remapped so that each XCD (workgroups are dealt round-robin
+// to the 8 XCDs) works on one contiguous range of centres, i.e. one spatial
+// region whose neighbour positions stay in that XCD's L2.
+__device__ inline int64_t xcd_remap(int64_t b, int64_t nb) {
+  const int64_t per = (nb + 7) / 8;
+  const int64_t x = b & 7, r = b >> 3;
+  const int64_t full = nb - (per - 1) * 8;  // XCDs that get `per` blocks (others per-1)
+  const int64_t start = x < full ? x * per : full * per + (x - full) * (per - 1);
+  return start + r;
+}
+
 // Number of set bits of mask below this lane.
 __device__ inline int lanes_below(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));

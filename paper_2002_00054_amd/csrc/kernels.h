@@ -67,6 +67,42 @@ void launch_triplet(int mode, int ne, const TripArgs<P>& a, hipStream_t stream);
 template <int P>
 size_t triplet_lds_bytes(int mode, int ne, int lcap);
 
+// ------------------------------------------------- stored-Jacobian form
+// J holds, for every centre c and neighbour slot t (entry e = c * cap + t),
+// the gradient of each SF s of c with respect to the neighbour's position:
+// J[(3 s + x) * plane + e], x = 0..2, plane = n * cap, s < n_sf(element of c).
+template <int P>
+struct JacArgs {
+  using T = typename Types<P>::T;
+  using IO = typename Types<P>::IO;
+  using FAcc = typename Types<P>::FAcc;
+  int64_t n;                 // sorted atoms
+  int cap;                   // neighbour slots per atom
+  int lcap;                  // >= the most neighbours of any atom
+  const typename Vec4<T>::type* nbr;  // [n][cap] (dx, dy, dz, j) entries
+  const int4* nnb;           // [n] neighbours per element block
+  const double4* pos4;       // sorted positions + ids
+  const DevTab<T>* tab;
+  int64_t plane;             // n * cap
+  T* J;                      // [3 * max n_sf][plane]
+  IO* G;                     // SF pass: G~ rows [n][LD]
+  const IO* C;               // force contraction: dE/dG rows [n][LD]
+  FAcc* F;                   // force contraction: accumulator [n][3] (sorted)
+  const IO* delta;           // JVP contraction: dL/dF [n][3] (sorted)
+  IO* V;                     // JVP contraction: rows [n][LD]
+};
+template <int P>
+void launch_jac(const JacArgs<P>& a, hipStream_t stream);          // G~ and J
+template <int P>
+size_t jac_lds_bytes(int lcap);
+template <int P>
+void launch_jac_force(const JacArgs<P>& a, hipStream_t stream);    // F from J and dE/dG
+template <int P>
+void launch_jac_jvp(const JacArgs<P>& a, hipStream_t stream);      // V from J and delta
+template <class IO>
+void launch_same_inputs(int64_t n, const IO* pos, const IO* saved_pos, const int32_t* types,
+                        const int32_t* saved_types, int* flag, hipStream_t stream);
+
 // ---------------------------------------------------------------- K4/K8
 template <int P>
 struct MlpArgs {
