@@ -163,6 +163,32 @@ nnp_status nnp_backward(nnp_handle* h, int n_struct, const int64_t* atom_offsets
                         const void* dL_dF, void* grad_params, void* stream);
 
 /*
+ * Molecular dynamics at constant N, V, E around the energy+force path, the
+ * setting the method is used in (Sec. 4: an MD proxy application, with energy
+ * conservation as its correctness check).  The paper does not name the
+ * integrator; this is velocity Verlet:
+ *   v += (dt/2) F/m;  x += dt v (then wrapped into [0, L));  F = F(x);  v += (dt/2) F/m.
+ * The neighbour list is rebuilt at every force evaluation.
+ *  n_atoms      atoms of one orthorhombic periodic structure
+ *  pos, vel     device [n_atoms][3], positions' type of the handle (FP64 for
+ *               NNP_FP64, else FP32), A and A/fs; advanced in place by n_steps
+ *  forces       device [n_atoms][3], same type; output: F at the final positions
+ *  types        device int32 [n_atoms]
+ *  box          host double[3], A
+ *  masses       host double[n_el], atomic mass units, finite and > 0
+ *  dt_fs        time step in fs, finite and > 0
+ *  n_steps      steps (>= 0; 0 evaluates the forces of the initial state only)
+ *  epot, ekin   host double [n_steps + 1] or NULL: potential and kinetic energy
+ *               (eV) of the initial state and after every step
+ * Updates are computed in FP64 and rounded once to the positions' type.  Unit
+ * conversions come from the CODATA electron volt and atomic mass constant.
+ * Synchronises the stream.  Errors as nnp_compute, checked before any step.
+ */
+nnp_status nnp_md_run(nnp_handle* h, int64_t n_atoms, void* pos, void* vel, void* forces, const int32_t* types,
+                      const double box[3], const double* masses, double dt_fs, int n_steps, double* epot,
+                      double* ekin, void* stream);
+
+/*
  * How the differentiation form obtains the SF derivatives dG_is/dr_m.
  *  NNP_DERIV_RECOMPUTE  (default) the force pass and nnp_backward recompute
  *                       them from the neighbour list, as the paper does

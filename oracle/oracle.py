@@ -10,7 +10,7 @@ Also holds the training-loss gradient of the differentiation form (loss of
 energies and forces, gradient with respect to every network parameter),
 written with plain float64 PyTorch autograd on the CPU over the per-atom
 networks, with the descriptor-Jacobian-vector products taken from the C++
-oracle.
+oracle; and a velocity Verlet integrator over the oracle's forces.
 """
 from __future__ import annotations
 
@@ -297,3 +297,44 @@ def loss_and_grad(pot: Potential, boxes, Ehat, Fhat, wF=0.1, nthreads=0):
     grads = torch.autograd.grad(total, params)
     flat = np.concatenate([g.detach().numpy().ravel() for g in grads])
     return L, flat
+
+
+# ---------------------------------------------------------------------------
+# Molecular dynamics at constant N, V, E (the setting of the method, Sec. 4)
+# ---------------------------------------------------------------------------
+# Unit conversions from the CODATA electron volt (J) and atomic mass constant
+# (kg), with 1 A = 1e-10 m and 1 fs = 1e-15 s.
+EV_J = 1.602176634e-19
+AMU_KG = 1.66053906660e-27
+ACCEL_CONV = (EV_J / 1e-10) / AMU_KG / (1e-10 / 1e-15 ** 2)  # eV/(A amu) -> A/fs^2
+KE_CONV = AMU_KG * (1e-10 / 1e-15) ** 2 / EV_J                # amu (A/fs)^2 -> eV
+
+
+def kinetic_energy(vel, m_atom):
+    """sum_i m_i |v_i|^2 / 2 in eV (vel in A/fs, masses in amu)."""
+    return 0.5 * KE_CONV * float(np.sum(m_atom[:, None] * vel * vel))
+
+
+def velocity_verlet(pot: Potential, pos, vel, types, box, masses, dt, n_steps, nthreads=0):
+    """Velocity Verlet, the textbook NVE integrator (the paper does not name
+    its integrator): half kick with F(t), drift by dt, forces at the new
+    positions, half kick with F(t + dt).  Positions are wrapped into [0, L)
+    after each drift.  Returns (pos, vel, F, epot[n+1], ekin[n+1]) in FP64."""
+    types = np.asarray(types)
+    box = np.asarray(box, dtype=np.float64)
+    m_atom = np.asarray(masses, dtype=np.float64)[types]
+    x = np.array(pos, dtype=np.float64)
+    v = np.array(vel, dtype=np.float64)
+    out = pot.compute(x, types, box, use_cells=True, nthreads=nthreads)
+    F = out["F"]
+    epot, ekin = [out["E"]], [kinetic_energy(v, m_atom)]
+    for _ in range(n_steps):
+        v = v + 0.5 * dt * ACCEL_CONV * F / m_atom[:, None]
+        x = x + dt * v
+        x = x - box * np.floor(x / box)
+        out = pot.compute(x, types, box, use_cells=True, nthreads=nthreads)
+        F = out["F"]
+        v = v + 0.5 * dt * ACCEL_CONV * F / m_atom[:, None]
+        epot.append(out["E"])
+        ekin.append(kinetic_energy(v, m_atom))
+    return x, v, F, np.array(epot), np.array(ekin)

@@ -736,6 +736,52 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
   return NNP_OK;
 }
 
+// Unit conversions of the MD driver from the CODATA values of the electron
+// volt (J), the atomic mass constant (kg) and the angstrom and femtosecond.
+constexpr double EV_J = 1.602176634e-19, AMU_KG = 1.66053906660e-27;
+constexpr double ACCEL_CONV = EV_J / 1e-10 / AMU_KG * 1e-30 / 1e-10;  // eV/(A amu) -> A/fs^2
+constexpr double KE_CONV = AMU_KG * 1e10 / EV_J;                       // amu A^2/fs^2 -> eV
+
+template <int P>
+nnp_status md_run(nnp_handle* h, int64_t n, void* pos_v, void* vel_v, void* f_v, const int32_t* types,
+                  const double box[3], const double* masses, double dt, int n_steps, double* epot, double* ekin,
+                  hipStream_t stream) {
+  using IO = typename Types<P>::IO;
+  IO* pos = reinterpret_cast<IO*>(pos_v);
+  IO* vel = reinterpret_cast<IO*>(vel_v);
+  IO* F = reinterpret_cast<IO*>(f_v);
+  MdArgs m;
+  std::memset(&m, 0, sizeof(m));
+  for (int e = 0; e < h->n_el; ++e) {
+    m.half_kick[e] = 0.5 * dt * ACCEL_CONV / masses[e];
+    m.half_mass[e] = 0.5 * masses[e];
+  }
+  m.dt = dt;
+  for (int x = 0; x < 3; ++x) {
+    m.L[x] = box[x];
+    m.invL[x] = 1.0 / box[x];
+  }
+  m.ke_conv = KE_CONV;
+  double *e_dev, *k_dev, *part;
+  nnp_status st;
+  if ((st = ensure_t(h, "md_epot", (size_t)n_steps + 1, &e_dev))) return st;
+  if ((st = ensure_t(h, "md_ekin", (size_t)n_steps + 1, &k_dev))) return st;
+  if ((st = ensure_t(h, "md_part", (size_t)md_blocks(n), &part))) return st;
+  const int64_t offs[2] = {0, n};
+  if ((st = forward<P>(h, 1, offs, pos, types, box, e_dev, nullptr, nullptr, F, stream))) return st;
+  launch_kick_ke<IO>(n, vel, F, types, m, false, part, k_dev, stream);
+  for (int s = 1; s <= n_steps; ++s) {
+    launch_kick_drift<IO>(n, pos, vel, F, types, m, stream);
+    if ((st = forward<P>(h, 1, offs, pos, types, box, e_dev + s, nullptr, nullptr, F, stream))) return st;
+    launch_kick_ke<IO>(n, vel, F, types, m, true, part, k_dev + s, stream);
+  }
+  if ((st = check_launch(h, "md"))) return st;
+  if (epot) NNP_HIP(h, hipMemcpyAsync(epot, e_dev, ((size_t)n_steps + 1) * sizeof(double), hipMemcpyDeviceToHost, stream));
+  if (ekin) NNP_HIP(h, hipMemcpyAsync(ekin, k_dev, ((size_t)n_steps + 1) * sizeof(double), hipMemcpyDeviceToHost, stream));
+  NNP_HIP(h, hipStreamSynchronize(stream));
+  return NNP_OK;
+}
+
 // --------------------------------------------------------------- create
 nnp_status build_table(nnp_handle* h, int n_el, int n_sf, const nnp_sf* sf, const nnp_net* nets) {
   DevTab<double>& t = h->tab_d;
@@ -1040,6 +1086,26 @@ int nnp_last_timings(const nnp_handle* h, const char** names, double* ms, int ma
     if (ms) ms[i] = h->t_ms[i];
   }
   return k;
+}
+
+nnp_status nnp_md_run(nnp_handle* h, int64_t n_atoms, void* pos, void* vel, void* forces, const int32_t* types,
+                      const double box[3], const double* masses, double dt_fs, int n_steps, double* epot,
+                      double* ekin, void* stream) {
+  if (!h) return NNP_E_ARG;
+  h->err.clear();
+  if (n_atoms < 0 || n_steps < 0) return fail(h, NNP_E_ARG, "n_atoms and n_steps must be >= 0");
+  if (n_atoms > 0 && (!pos || !vel || !forces || !types))
+    return fail(h, NNP_E_ARG, "pos, vel, forces and types must not be NULL");
+  if (!box || !masses) return fail(h, NNP_E_ARG, "box and masses must not be NULL");
+  if (!(std::isfinite(dt_fs) && dt_fs > 0.0)) return fail(h, NNP_E_ARG, "dt must be finite and > 0");
+  for (int e = 0; e < h->n_el; ++e)
+    if (!(std::isfinite(masses[e]) && masses[e] > 0.0)) return fail(h, NNP_E_ARG, "masses must be finite and > 0");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  switch (h->prec) {
+    case NNP_FP64: return md_run<P_FP64>(h, n_atoms, pos, vel, forces, types, box, masses, dt_fs, n_steps, epot, ekin, s);
+    case NNP_FP32: return md_run<P_FP32>(h, n_atoms, pos, vel, forces, types, box, masses, dt_fs, n_steps, epot, ekin, s);
+    default: return md_run<P_BF16>(h, n_atoms, pos, vel, forces, types, box, masses, dt_fs, n_steps, epot, ekin, s);
+  }
 }
 
 nnp_status nnp_set_derivative_mode(nnp_handle* h, int mode) {

@@ -103,6 +103,22 @@ template <class IO>
 void launch_same_inputs(int64_t n, const IO* pos, const IO* saved_pos, const int32_t* types,
                         const int32_t* saved_types, int* flag, hipStream_t stream);
 
+// ------------------------------------------------------ velocity Verlet
+struct MdArgs {
+  double half_kick[MAX_EL];  // (dt / 2) accel_conv / m_e
+  double half_mass[MAX_EL];  // m_e / 2
+  double dt;                 // fs
+  double L[3], invL[3];      // box edges (A) and inverses
+  double ke_conv;            // amu A^2 / fs^2 -> eV
+};
+int md_blocks(int64_t n);    // blocks of the kinetic-energy partial sums
+template <class IO>
+void launch_kick_drift(int64_t n, IO* pos, IO* vel, const IO* F, const int32_t* types, const MdArgs& m,
+                       hipStream_t stream);
+template <class IO>
+void launch_kick_ke(int64_t n, IO* vel, const IO* F, const int32_t* types, const MdArgs& m, bool kick,
+                    double* partial, double* ke_out, hipStream_t stream);
+
 // ---------------------------------------------------------------- K4/K8
 template <int P>
 struct MlpArgs {

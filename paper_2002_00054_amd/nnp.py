@@ -23,7 +23,8 @@ STATUS = {0: "NNP_OK", -1: "NNP_E_ARG", -2: "NNP_E_BOX", -3: "NNP_E_TYPE", -4: "
 #: Every symbol include/nnp.h declares.
 EXPORTS = ("nnp_create", "nnp_compute", "nnp_compute_batch", "nnp_backward", "nnp_n_params", "nnp_set_params",
            "nnp_get_params", "nnp_set_profiling", "nnp_last_timings", "nnp_neighbor_capacity",
-           "nnp_set_neighbor_capacity", "nnp_count_work", "nnp_set_derivative_mode", "nnp_workspace_bytes",
+           "nnp_set_neighbor_capacity", "nnp_count_work", "nnp_md_run", "nnp_set_derivative_mode",
+           "nnp_workspace_bytes",
            "nnp_destroy", "nnp_last_error")
 DERIV_MODES = {"recompute": 0, "stored": 1}
 
@@ -76,6 +77,7 @@ def load_library(path: str = LIB_PATH):
     L.nnp_neighbor_capacity.argtypes = [vp]
     L.nnp_set_neighbor_capacity.argtypes = [vp, C.c_int]
     L.nnp_count_work.argtypes = [vp, i64, vp, vp, dp, C.POINTER(i64), vp]
+    L.nnp_md_run.argtypes = [vp, i64, vp, vp, vp, vp, dp, dp, C.c_double, C.c_int, dp, dp, vp]
     L.nnp_set_derivative_mode.argtypes = [vp, C.c_int]
     L.nnp_workspace_bytes.argtypes = [vp]
     L.nnp_workspace_bytes.restype = i64
@@ -85,7 +87,7 @@ def load_library(path: str = LIB_PATH):
     L.nnp_last_error.restype = C.c_char_p
     for name in ("nnp_create", "nnp_compute", "nnp_compute_batch", "nnp_backward", "nnp_set_params",
                  "nnp_get_params", "nnp_set_profiling", "nnp_set_neighbor_capacity", "nnp_last_timings",
-                 "nnp_neighbor_capacity", "nnp_count_work", "nnp_set_derivative_mode"):
+                 "nnp_neighbor_capacity", "nnp_count_work", "nnp_md_run", "nnp_set_derivative_mode"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -244,6 +246,29 @@ class Potential:
                                          _ptr(types), bx.ctypes.data_as(C.POINTER(C.c_double)), _ptr(dL_dE),
                                          _ptr(dL_dF), _ptr(g), _stream_ptr(stream)))
         return g
+
+    def md_run(self, pos, vel, types, box, masses, dt, n_steps, stream=None):
+        """Velocity Verlet: advances the device tensors pos and vel in place by
+        n_steps steps of dt fs (A, A/fs, amu per element); returns the forces
+        at the final positions and the potential and kinetic energies (eV) of
+        the initial state and after every step."""
+        import torch
+
+        pos, types = self._prep(pos, types)
+        if vel.dtype != self.dtype or not vel.is_cuda or not vel.is_contiguous() or vel.shape != pos.shape:
+            raise TypeError("vel must be a contiguous device tensor shaped and typed like pos")
+        if not pos.is_contiguous():
+            raise TypeError("pos must be contiguous (it is updated in place)")
+        n = pos.shape[0]
+        f = torch.empty((n, 3), dtype=self.dtype, device=pos.device)
+        boxa = (C.c_double * 3)(*[float(x) for x in box])
+        m = (C.c_double * self.n_el)(*[float(x) for x in masses])
+        ep = np.zeros(n_steps + 1)
+        ek = np.zeros(n_steps + 1)
+        self._check(self._L.nnp_md_run(self._h, n, _ptr(pos), _ptr(vel), _ptr(f), _ptr(types), boxa, m, float(dt),
+                                       int(n_steps), ep.ctypes.data_as(C.POINTER(C.c_double)),
+                                       ek.ctypes.data_as(C.POINTER(C.c_double)), _stream_ptr(stream)))
+        return f, ep, ek
 
     def count_work(self, pos, types, box, stream=None) -> dict:
         """Neighbour entries, candidate neighbour pairs and triplet terms of

@@ -139,6 +139,20 @@ CONFIG1 = dict(n=16, seeds=(11, 12, 13))  # 12,288 atoms, 49.68 A
 CONFIG2 = dict(n=88, seed=22)  # 2,044,416 atoms, 273.24 A
 SWEEP_N = (16, 24, 32, 44, 56, 70, 88)  # weak-scaling sweep, seed 100 + n
 
+# Standard atomic weights of H and O (amu), the masses of the MD runs.
+WATER_MASSES = (1.00794, 15.9994)
+
+
+def thermal_velocities(types: np.ndarray, masses=WATER_MASSES, temperature: float = 300.0,
+                       seed: int = 0) -> np.ndarray:
+    """Seeded initial velocities (A/fs): each component N(0, kB T / m) with
+    kB = 8.617333262e-5 eV/K and 1 amu (A/fs)^2 = 103.6427 eV, the centre of
+    mass at rest."""
+    m = np.asarray(masses, dtype=np.float64)[np.asarray(types)]
+    sigma = np.sqrt(8.617333262e-5 * temperature / (m * 103.64269652680505))
+    v = np.random.default_rng(seed).normal(size=(len(m), 3)) * sigma[:, None]
+    return v - np.sum(m[:, None] * v, axis=0) / np.sum(m)
+
 
 def training_batch_sizes(n_struct: int = 32, seed: int = 4) -> np.ndarray:
     """Lattice sides n in {4..8} of the uneven training batch (192-1536 atoms)."""
