@@ -98,7 +98,8 @@ def cpu_baseline(table, nets, budget_s=12.0, nthreads=0):
 
 def report(table, nets):
     """Extra JSON lines instead of the contract line: the measured device peaks,
-    every form over the size sweep, the training step of the differentiation
+    every form over the size sweep, the single-element fcc workload (3.9 A
+    cutoff, up to 1,492,992 atoms), the training step of the differentiation
     form (32 uneven boxes, loss = energy MSE + 0.1 force MSE, synthetic
     targets) with recomputed and with stored SF derivatives, the forward with
     each, velocity Verlet MD steps (throughput and energy drift), and the CPU
@@ -120,6 +121,28 @@ def report(table, nets):
             ms, st = time_form(pot, x, t, bb.box, 10 if side < 64 else 5, 2)
             print(json.dumps({"report": "sweep", "form": form, "atoms": bb.n_atoms, "ms_per_step": ms,
                               "atom_steps_per_s": bb.n_atoms / (ms * 1e-3), "stages_ms": st}), flush=True)
+            del x, t
+        pot.close()
+        torch.cuda.empty_cache()
+    # second workload: single-element fcc metal, 3.9 A cutoff (the paper's Ni runs: ~1.5M atoms)
+    from paper_2002_00054_amd import opcount
+
+    ni_table, ni_nets = synth.ni_table_scaled(), synth.ni_nets()
+    for form in ("fp32", "fp64", "bf16"):
+        pot = Potential(ni_table, ni_nets, precision=form, elements=("Ni",))
+        for side in ((20, 40, 72) if form == "fp32" else (72,)):
+            bb = synth.fcc_box(side, side)
+            x = torch.tensor(bb.pos, dtype=pot.dtype, device=dev)
+            t = torch.tensor(bb.types, dtype=torch.int32, device=dev)
+            ms, st = time_form(pot, x, t, bb.box, 10, 2)
+            line = {"report": "ni", "form": form, "atoms": bb.n_atoms, "ms_per_step": ms,
+                    "atom_steps_per_s": bb.n_atoms / (ms * 1e-3), "stages_ms": st}
+            if form == "fp32" and side == 72:
+                counts = pot.count_work(x, t, bb.box)
+                line["work_counts"] = counts
+                line["force_tflops"] = opcount.flops(opcount.FORCE, counts) / (st["force"] * 1e-3) / 1e12
+                line["sf_tflops"] = opcount.flops(opcount.SF, counts) / (st["sf"] * 1e-3) / 1e12
+            print(json.dumps(line), flush=True)
             del x, t
         pot.close()
         torch.cuda.empty_cache()

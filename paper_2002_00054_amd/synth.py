@@ -336,3 +336,70 @@ def water_table_scaled(path: str | None = None) -> list[SF]:
         s.scale = float(sc["scale"][ELEMENTS[e]][k])
         counters[e] += 1
     return table
+
+
+# --------------------------------------------------------------------------
+# Second workload: a single-element fcc metal with a short cutoff (Ni-like)
+# --------------------------------------------------------------------------
+#: fcc lattice constant (A), cutoff of the paper's Ni model (A), displacement
+#: half-width (A) of each coordinate, and the atomic weight (amu).
+NI_LATTICE = 3.52
+NI_RCUT = 3.9
+NI_JITTER = 0.1
+NI_MASS = 58.6934
+#: fcc basis in units of the lattice constant.
+FCC_BASIS = ((0.0, 0.0, 0.0), (0.5, 0.5, 0.0), (0.5, 0.0, 0.5), (0.0, 0.5, 0.5))
+
+
+def fcc_box(n: int, seed: int, a: float = NI_LATTICE, jitter: float = NI_JITTER) -> Box:
+    """n^3 cubic cells of 4 atoms (L = n a), every coordinate displaced by
+    U(+-jitter) drawn from ``default_rng(seed)``, all atoms of type 0, sites in
+    C order of the cells then the basis, wrapped into [0, L)."""
+    ijk = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"), axis=-1).reshape(-1, 3)
+    pos = ((ijk[:, None, :] + np.asarray(FCC_BASIS)[None, :, :]) * a).reshape(-1, 3)
+    if jitter > 0:
+        pos = pos + np.random.default_rng(seed).uniform(-jitter, jitter, size=pos.shape)
+    L = n * a
+    box = np.array([L, L, L])
+    pos = np.mod(pos, box)
+    pos[pos >= L] = 0.0
+    return Box(pos=pos, types=np.zeros(len(pos), dtype=np.int32), box=box, seed=seed, n_side=n)
+
+
+#: Radial exponents of the Ni table (A^-2): 0.003 * 500^(k/7), k = 0..7.
+NI_RADIAL_ETAS = tuple(0.003 * 500.0 ** (k / 7.0) for k in range(8))
+#: Angular list of the Ni table: (eta [A^-2], zeta, lambda); the same (zeta,
+#: lambda, eta-index) structure as the water table's base list.
+NI_ANGULAR = (
+    (0.003, 1, -1.0),
+    (0.003, 1, +1.0),
+    (0.003, 4, -1.0),
+    (0.003, 4, +1.0),
+    (0.05, 2, +1.0),
+    (0.05, 16, +1.0),
+)
+
+
+def ni_sf_table() -> list[SF]:
+    """14 SFs of the single element: 8 radial (eta ascending), then 6 narrow angular."""
+    table = [SF(0, 2, (0,), eta, rc=NI_RCUT) for eta in NI_RADIAL_ETAS]
+    table += [SF(0, 3, (0, 0), eta, 0.0, float(zeta), lam, rc=NI_RCUT) for eta, zeta, lam in NI_ANGULAR]
+    return table
+
+
+def ni_nets(seed: int = 2000) -> list[Net]:
+    return xavier_nets(sf_counts(ni_sf_table(), n_el=1), seed)
+
+
+def ni_table_scaled(path: str | None = None) -> list[SF]:
+    """``ni_sf_table`` with the stored shift/scale filled in."""
+    import os
+
+    if path is None:
+        path = os.path.join(os.path.dirname(__file__), "data", "ni_scaling.json")
+    sc = load_scaling(path)
+    table = ni_sf_table()
+    for k, s in enumerate(table):
+        s.shift = float(sc["shift"]["Ni"][k])
+        s.scale = float(sc["scale"]["Ni"][k])
+    return table
