@@ -66,15 +66,16 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(table, nets, budget_s=12.0, nthreads=0):
-    """The FP64 oracle on a 12,288-atom box of the same generator and density
-    (nthreads = 0: every thread OpenMP gets on this host)."""
+def cpu_baseline(table, nets, budget_s=12.0, nthreads=0, workload="water"):
+    """The FP64 oracle on a 12,288-atom water box (or a 32,000-atom fcc box for
+    the second workload) of the same generator and density (nthreads = 0:
+    every thread OpenMP gets on this host)."""
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle
     from paper_2002_00054_amd import synth
 
-    pot = oracle.Potential(table, nets)
-    b = synth.water_box(16, 11)
+    pot = oracle.Potential(table, nets, n_el=len(nets))
+    b = synth.water_box(16, 11) if workload == "water" else synth.fcc_box(20, 3)
     times = []
     t_start = time.perf_counter()
     while True:
@@ -90,9 +91,12 @@ def cpu_baseline(table, nets, budget_s=12.0, nthreads=0):
         "unit": "atom-steps/s",
         "cores": nthreads if nthreads > 0 else oracle.max_threads(),
         "kind": "oracle",
-        "sample": f"median of {len(times)} full energy+force evaluations (cell-list neighbours) of a "
-                  f"12,288-atom water box (lattice side 16, seed 11; same generator, density and cutoff "
-                  f"as the 2,044,416-atom workload), FP64 C++ oracle with OpenMP",
+        "sample": (f"median of {len(times)} full energy+force evaluations (cell-list neighbours) of a "
+                   f"12,288-atom water box (lattice side 16, seed 11; same generator, density and cutoff "
+                   f"as the 2,044,416-atom workload), FP64 C++ oracle with OpenMP") if workload == "water" else
+                  (f"median of {len(times)} full energy+force evaluations (cell-list neighbours) of a "
+                   f"32,000-atom fcc box (20 cells per axis, seed 3; same generator and cutoff as the "
+                   f"1,492,992-atom workload), FP64 C++ oracle with OpenMP"),
     }
 
 
@@ -226,8 +230,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n-side", type=int, default=88, help="lattice side (atoms = 3 n^3)")
-    ap.add_argument("--seed", type=int, default=22)
+    ap.add_argument("--workload", choices=("water", "ni"), default="water",
+                    help="water (the benchmark) or the single-element fcc metal at 3.9 A (second workload)")
+    ap.add_argument("--n-side", type=int, default=None,
+                    help="lattice side (water: 3 n^3 atoms, default 88; fcc: 4 n^3 atoms, default 72)")
+    ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--forms", default="fp64,bf16", help="extra forms timed beside FP32 (comma list, '' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--report", action="store_true",
@@ -259,14 +266,23 @@ def main():
     if args.report:
         report(table, nets)
         return
-    b = synth.water_box(args.n_side, args.seed)
+    water = args.workload == "water"
+    if args.n_side is None:
+        args.n_side = 88 if water else 72
+    if args.seed is None:
+        args.seed = 22 if water else args.n_side
+    if water:
+        b = synth.water_box(args.n_side, args.seed)
+    else:
+        table, nets = synth.ni_table_scaled(), synth.ni_nets()
+        b = synth.fcc_box(args.n_side, args.seed)
     n = b.n_atoms
     dev = torch.device("cuda:0")
     types = torch.tensor(b.types, dtype=torch.int32, device=dev)
     pos32 = torch.tensor(b.pos, dtype=torch.float32, device=dev)
     print(f"# workload: {n} atoms, box {b.box[0]:.2f} A", file=sys.stderr, flush=True)
 
-    pot = Potential(table, nets, precision="fp32")
+    pot = Potential(table, nets, precision="fp32", elements=("H", "O") if water else ("Ni",))
     ms, stages = time_form(pot, pos32, types, b.box, args.steps, args.warmup)
     print(f"# fp32: {ms:.3f} ms/step, stages {stages}", file=sys.stderr, flush=True)
     counts = pot.count_work(pos32, types, b.box)
@@ -278,7 +294,7 @@ def main():
     peak = opcount.PEAK_FP32_VECTOR_TFLOPS
     traffic = None
     src = kernel_source_hash()
-    if os.path.exists(TRAFFIC_FILE):
+    if water and os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
         if tr.get("source_hash") == src:
@@ -286,7 +302,7 @@ def main():
 
     forms = {}
     for form in [f for f in args.forms.split(",") if f]:
-        p2 = Potential(table, nets, precision=form)
+        p2 = Potential(table, nets, precision=form, elements=("H", "O") if water else ("Ni",))
         x = pos32 if p2.dtype == torch.float32 else torch.tensor(b.pos, dtype=p2.dtype, device=dev)
         ms2, st2 = time_form(p2, x, types, b.box, max(2, args.steps // 3), 1)
         forms[form] = {"value": n / (ms2 * 1e-3), "ms_per_step": ms2, "stages_ms": st2}
@@ -296,7 +312,7 @@ def main():
         torch.cuda.empty_cache()
 
     out = {
-        "metric": METRIC,
+        "metric": METRIC if water else "atom-steps/s energy+forces, 1.5M-atom fcc metal, 3.9 A cutoff",
         "value": n / (ms * 1e-3),
         "unit": "atom-steps/s",
         "n_gpus": 1,
@@ -308,9 +324,12 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": f"water box {n} atoms ({n // 3} H2O, lattice side {args.n_side}, "
-                               f"L={b.box[0]:.2f} A, seed {args.seed}), rc 6 A, H 27 / O 30 SFs, "
-                               f"nets SF-25-25-1 tanh, neighbour list rebuilt every step",
+        "config": {"workload": (f"water box {n} atoms ({n // 3} H2O, lattice side {args.n_side}, "
+                                f"L={b.box[0]:.2f} A, seed {args.seed}), rc 6 A, H 27 / O 30 SFs, "
+                                f"nets SF-25-25-1 tanh, neighbour list rebuilt every step") if water else
+                               (f"fcc box {n} atoms ({args.n_side} cells per axis, a=3.52 A, L={b.box[0]:.2f} A, "
+                                f"seed {args.seed}), rc 3.9 A, 14 SFs, nets SF-25-25-1 tanh, neighbour list "
+                                f"rebuilt every step"),
                    "form": "FP32 plain"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic, "kernel": "k_triplet<FP32, force>",
@@ -322,7 +341,7 @@ def main():
         "forms": forms,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(table, nets)
+        out["cpu_baseline"] = cpu_baseline(table, nets, workload=args.workload)
     print(json.dumps(out), flush=True)
 
 

@@ -78,3 +78,32 @@ def test_ni_fullsize_sampled(form):
         assert np.max(np.abs(np.sum(f, axis=0))) < 0.05
     assert abs(e - float(np.sum(ei))) <= 1e-12 * abs(e) + 1e-9
     pot.close()
+
+
+def test_ni_weight_gradient_matches_oracle():
+    """Differentiation form on the second workload (10,976 + 108 atoms: the
+    triplet kernels' multi-centre waves in the SF, force and JVP passes)."""
+    import torch
+
+    from paper_2002_00054_amd.nnp import energy_forces
+
+    table, nets = synth.ni_table_scaled(), synth.ni_nets()
+    teacher = synth.xavier_nets(synth.sf_counts(table, n_el=1), 7, bias_halfwidth=0.1)
+    boxes = [synth.fcc_box(14, 5), synth.fcc_box(3, 6)]
+    Ehat, Fhat = oracle.batch_energy_forces(oracle.Potential(table, teacher, n_el=1), boxes)
+    L_ref, g_ref = oracle.loss_and_grad(oracle.Potential(table, nets, n_el=1), boxes, Ehat, Fhat)
+    pot = make_potential("fp64", table, nets)
+    pos = torch.tensor(np.concatenate([b.pos for b in boxes]), dtype=torch.float64, device="cuda")
+    types = torch.tensor(np.concatenate([b.types for b in boxes]), dtype=torch.int32, device="cuda")
+    offs = np.cumsum([0] + [b.n_atoms for b in boxes])
+    th = torch.tensor(synth.flat_params(nets), dtype=torch.float64, device="cuda", requires_grad=True)
+    E, F = energy_forces(th, pos, pot, types, offs, np.stack([b.box for b in boxes]))
+    N = torch.tensor([b.n_atoms for b in boxes], dtype=torch.float64, device="cuda")
+    L = torch.mean(((E - torch.tensor(Ehat, device="cuda")) / N) ** 2) + \
+        0.1 * torch.sum((F - torch.tensor(Fhat, device="cuda")) ** 2) / (3 * N.sum())
+    (g,) = torch.autograd.grad(L, th)
+    rel = float(np.linalg.norm(g.cpu().numpy() - g_ref) / np.linalg.norm(g_ref))
+    say("ni fp64 weight-gradient rel-L2", rel)
+    assert rel < 1e-8
+    assert L.item() == pytest.approx(L_ref, rel=1e-10)
+    pot.close()
