@@ -150,6 +150,20 @@ def report(table, nets):
             del x, t
         pot.close()
         torch.cuda.empty_cache()
+    # level of parallelism of the SF and force passes: a wave per centre against a thread per centre
+    for wl, bb, tb, nt in (("ni", synth.fcc_box(72, 72), ni_table, ni_nets),
+                           ("water", synth.water_box(88, 22), table, nets)):
+        for mode in ("wave", "thread"):
+            pot = Potential(tb, nt, precision="fp32", elements=("Ni",) if wl == "ni" else ("H", "O"))
+            pot.set_parallelism(mode)
+            x = torch.tensor(bb.pos, dtype=torch.float32, device=dev)
+            t = torch.tensor(bb.types, dtype=torch.int32, device=dev)
+            ms, st = time_form(pot, x, t, bb.box, 5 if mode == "wave" else 3, 1)
+            print(json.dumps({"report": "parallelism", "workload": wl, "form": "fp32", "level": mode,
+                              "atoms": bb.n_atoms, "ms_per_step": ms, "stages_ms": st}), flush=True)
+            pot.close()
+            del x, t
+            torch.cuda.empty_cache()
     # differentiation form: one training step = forward of the batch + loss + weight gradient
     boxes = synth.training_batch()
     offs = np.cumsum([0] + [bx.n_atoms for bx in boxes])

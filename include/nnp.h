@@ -189,6 +189,21 @@ nnp_status nnp_md_run(nnp_handle* h, int64_t n_atoms, void* pos, void* vel, void
                       double* ekin, void* stream);
 
 /*
+ * Level of parallelism of the SF and force passes (the paper's Sec. 4.3
+ * question of threading over atoms only or over atoms and neighbours).
+ *  NNP_PAR_WAVE    one 64-lane wavefront per centre atom: lanes over its
+ *                  neighbours, then over its neighbour pairs.
+ *  NNP_PAR_THREAD  one thread per centre atom, walking its neighbours and
+ *                  pairs alone (the paper's flat level); kept for comparison.
+ *  NNP_PAR_AUTO    (default) the faster level; on this device that is a
+ *                  wave per centre for long and short neighbour rows alike.
+ * Both give the same results up to rounding order.  The force-adjoint pass of
+ * nnp_backward always runs wave per centre.  An unknown mode is NNP_E_ARG.
+ */
+typedef enum { NNP_PAR_AUTO = 0, NNP_PAR_WAVE = 1, NNP_PAR_THREAD = 2 } nnp_parallelism;
+nnp_status nnp_set_parallelism(nnp_handle* h, int mode);
+
+/*
  * How the differentiation form obtains the SF derivatives dG_is/dr_m.
  *  NNP_DERIV_RECOMPUTE  (default) the force pass and nnp_backward recompute
  *                       them from the neighbour list, as the paper does

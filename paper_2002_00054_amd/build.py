@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnnp.so")
-SOURCES = ["api.hip", "k_neighbor.hip", "k_misc.hip", "k_mlp.hip", "k_jacobian.hip", "k_md.hip",
+SOURCES = ["api.hip", "k_neighbor.hip", "k_misc.hip", "k_mlp.hip", "k_jacobian.hip", "k_md.hip", "k_flat.hip",
            "k_triplet_f64.hip", "k_triplet_f32.hip", "k_triplet_bf16.hip"]
 PEAKS_LIB = os.path.join(HERE, "libnnp_peaks.so")
 PEAKS_SOURCES = ["peaks.hip"]

@@ -59,6 +59,7 @@ struct nnp_handle {
   bool has_forward = false;
   // stored-Jacobian differentiation form: the last forward's inputs, for
   // reuse of its J store by nnp_backward
+  int parallelism = NNP_PAR_AUTO;        // SF and force passes: wave or thread per centre
   int deriv_mode = NNP_DERIV_RECOMPUTE;
   bool jac_valid = false;
   int jac_cap = 0;
@@ -440,6 +441,10 @@ int check_flags(nnp_handle* h, hipStream_t stream, Common& cm, nnp_status* st) {
   return 0;
 }
 
+// Thread per centre for the SF and force passes only when asked for: a wave
+// per centre was measured faster on both workloads, short rows included.
+bool flat_passes(const nnp_handle* h) { return h->parallelism == NNP_PAR_THREAD; }
+
 // The stored-Jacobian form applies to the FP64 and FP32 handles.
 template <int P>
 bool stored_jacobian(const nnp_handle* h) {
@@ -582,20 +587,23 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
       }
     }
     if (!stored) {
+      const bool flat = flat_passes(h);
       const size_t lds =
           std::max(triplet_lds_bytes<P>(0, h->variant, h->lcap), triplet_lds_bytes<P>(1, h->variant, h->lcap));
-      if (lds > lds_limit())
+      if (!flat && lds > lds_limit())
         return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) + " neighbours needs " +
                                       std::to_string(lds) + " bytes of LDS per workgroup, more than the device allows");
       ta.G = G;
-      launch_triplet<P>(0, h->variant, ta, stream);
+      if (flat) launch_flat<P>(0, ta, stream);
+      else launch_triplet<P>(0, h->variant, ta, stream);
       mk.mark("sf");
       launch_fill<FAcc>(F_s, n * 3, FAcc(0), stream);
       launch_mlp<P>(ma, stream);
       mk.mark("mlp");
       ta.C = C;
       ta.F = F_s;
-      launch_triplet<P>(1, h->variant, ta, stream);
+      if (flat) launch_flat<P>(1, ta, stream);
+      else launch_triplet<P>(1, h->variant, ta, stream);
       mk.mark("force");
     }
     launch_unpermute<IO, FAcc>(n, cm.bin.perm, Ei_s, F_s, Ei_o, reinterpret_cast<IO*>(ei_v),
@@ -684,7 +692,8 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
         return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) +
                                       " neighbours needs more LDS per workgroup than the device allows");
       ta.G = G;
-      launch_triplet<P>(0, h->variant, ta, stream);
+      if (flat_passes(h)) launch_flat<P>(0, ta, stream);
+      else launch_triplet<P>(0, h->variant, ta, stream);
       mk.mark("sf");
     }
     ready = true;
@@ -1106,6 +1115,15 @@ nnp_status nnp_md_run(nnp_handle* h, int64_t n_atoms, void* pos, void* vel, void
     case NNP_FP32: return md_run<P_FP32>(h, n_atoms, pos, vel, forces, types, box, masses, dt_fs, n_steps, epot, ekin, s);
     default: return md_run<P_BF16>(h, n_atoms, pos, vel, forces, types, box, masses, dt_fs, n_steps, epot, ekin, s);
   }
+}
+
+nnp_status nnp_set_parallelism(nnp_handle* h, int mode) {
+  if (!h) return NNP_E_ARG;
+  h->err.clear();
+  if (mode != NNP_PAR_AUTO && mode != NNP_PAR_WAVE && mode != NNP_PAR_THREAD)
+    return fail(h, NNP_E_ARG, "parallelism must be NNP_PAR_AUTO, NNP_PAR_WAVE or NNP_PAR_THREAD");
+  h->parallelism = mode;
+  return NNP_OK;
 }
 
 nnp_status nnp_set_derivative_mode(nnp_handle* h, int mode) {

@@ -64,6 +64,9 @@ struct TripArgs {
 
 template <int P>
 void launch_triplet(int mode, int ne, const TripArgs<P>& a, hipStream_t stream);
+// One thread per centre (mode 0: SF, 1: force), for short neighbour rows.
+template <int P>
+void launch_flat(int mode, const TripArgs<P>& a, hipStream_t stream);
 template <int P>
 size_t triplet_lds_bytes(int mode, int ne, int lcap);
 

@@ -23,10 +23,12 @@ STATUS = {0: "NNP_OK", -1: "NNP_E_ARG", -2: "NNP_E_BOX", -3: "NNP_E_TYPE", -4: "
 #: Every symbol include/nnp.h declares.
 EXPORTS = ("nnp_create", "nnp_compute", "nnp_compute_batch", "nnp_backward", "nnp_n_params", "nnp_set_params",
            "nnp_get_params", "nnp_set_profiling", "nnp_last_timings", "nnp_neighbor_capacity",
-           "nnp_set_neighbor_capacity", "nnp_count_work", "nnp_md_run", "nnp_set_derivative_mode",
+           "nnp_set_neighbor_capacity", "nnp_count_work", "nnp_md_run", "nnp_set_parallelism",
+           "nnp_set_derivative_mode",
            "nnp_workspace_bytes",
            "nnp_destroy", "nnp_last_error")
 DERIV_MODES = {"recompute": 0, "stored": 1}
+PARALLELISM = {"auto": 0, "wave": 1, "thread": 2}
 
 
 class NNPError(RuntimeError):
@@ -78,6 +80,7 @@ def load_library(path: str = LIB_PATH):
     L.nnp_set_neighbor_capacity.argtypes = [vp, C.c_int]
     L.nnp_count_work.argtypes = [vp, i64, vp, vp, dp, C.POINTER(i64), vp]
     L.nnp_md_run.argtypes = [vp, i64, vp, vp, vp, vp, dp, dp, C.c_double, C.c_int, dp, dp, vp]
+    L.nnp_set_parallelism.argtypes = [vp, C.c_int]
     L.nnp_set_derivative_mode.argtypes = [vp, C.c_int]
     L.nnp_workspace_bytes.argtypes = [vp]
     L.nnp_workspace_bytes.restype = i64
@@ -87,7 +90,8 @@ def load_library(path: str = LIB_PATH):
     L.nnp_last_error.restype = C.c_char_p
     for name in ("nnp_create", "nnp_compute", "nnp_compute_batch", "nnp_backward", "nnp_set_params",
                  "nnp_get_params", "nnp_set_profiling", "nnp_set_neighbor_capacity", "nnp_last_timings",
-                 "nnp_neighbor_capacity", "nnp_count_work", "nnp_md_run", "nnp_set_derivative_mode"):
+                 "nnp_neighbor_capacity", "nnp_count_work", "nnp_md_run", "nnp_set_parallelism",
+                 "nnp_set_derivative_mode"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -166,6 +170,10 @@ class Potential:
     @property
     def n_params(self) -> int:
         return int(self._L.nnp_n_params(self._h))
+
+    def set_parallelism(self, mode: str):
+        """SF and force passes: "auto" (default), "wave" or "thread" per centre."""
+        self._check(self._L.nnp_set_parallelism(self._h, PARALLELISM[mode]))
 
     def set_derivative_mode(self, mode: str):
         """"recompute" (default) or "stored" (keep dG/dr per neighbour slot)."""

@@ -1,0 +1,72 @@
+"""Both levels of parallelism of the SF and force passes (nnp_set_parallelism)
+against the FP64 oracle, on both workloads: one thread per centre on the
+water boxes (86 neighbours) and on the fcc boxes (18 neighbours), one wave
+per centre (also the default) named explicitly on the fcc boxes, at the
+usual bars, and the two levels against each other."""
+import numpy as np
+import pytest
+
+import oracle
+from common import oracle_water
+from gpu_common import check_fp32, check_fp64, make_potential, oracle_input, run, say
+from paper_2002_00054_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("side,seed", [(4, 1), (16, 11)])
+def test_water_thread_per_centre(form, side, seed):
+    b = synth.water_box(side, seed)
+    say("water thread", form, b.n_atoms)
+    pot = make_potential(form)
+    pot.set_parallelism("thread")
+    e, ei, f = run(pot, b)
+    ref = oracle_water().compute(oracle_input(b, form), b.types, b.box, use_cells=True)
+    if form == "fp64":
+        check_fp64(ei, f, ref["Ei"], ref["F"])
+    elif form == "fp32":
+        check_fp32(ei, f, ref["Ei"], ref["F"])
+    else:
+        assert float(np.sqrt(np.mean((f - ref["F"]) ** 2))) <= 5e-3
+    pot.close()
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("mode", ["wave", "thread"])
+def test_fcc_levels(form, mode):
+    table, nets = synth.ni_table_scaled(), synth.ni_nets()
+    b = synth.fcc_box(8, 2)
+    pot = make_potential(form, table, nets)
+    pot.set_parallelism(mode)
+    e, ei, f = run(pot, b)
+    ref = oracle.Potential(table, nets, n_el=1).compute(oracle_input(b, form), b.types, b.box, use_cells=True)
+    if form == "fp64":
+        check_fp64(ei, f, ref["Ei"], ref["F"])
+    else:
+        check_fp32(ei, f, ref["Ei"], ref["F"])
+    pot.close()
+
+
+def test_levels_agree_fp64():
+    table, nets = synth.ni_table_scaled(), synth.ni_nets()
+    b = synth.fcc_box(20, 3)
+    out = {}
+    for mode in ("wave", "thread"):
+        pot = make_potential("fp64", table, nets)
+        pot.set_parallelism(mode)
+        out[mode] = run(pot, b)
+        pot.close()
+    (e1, ei1, f1), (e2, ei2, f2) = out["wave"], out["thread"]
+    assert e2 == pytest.approx(e1, rel=1e-13)
+    assert np.max(np.abs(ei2 - ei1)) < 1e-12 * np.max(np.abs(ei1))
+    assert np.max(np.abs(f2 - f1)) < 1e-12 * np.max(np.abs(f1))
+
+
+def test_bad_mode():
+    from paper_2002_00054_amd.nnp import NNPError
+
+    pot = make_potential("fp32")
+    with pytest.raises(NNPError, match="NNP_E_ARG"):
+        pot._check(pot._L.nnp_set_parallelism(pot._h, 9))
+    pot.close()
