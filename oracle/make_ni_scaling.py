@@ -1,4 +1,5 @@
-"""Write the frozen centring/scaling constants of the Ni SF table.
+"""Write the frozen centring/scaling constants of the Ni SF tables (narrow
+and wide angular).
 
 As for water: for every SF the shift is the mean and the scale the range
 (max - min) of the raw SF over the 256 atoms of the reference fcc box
@@ -20,24 +21,30 @@ sys.path.insert(0, os.path.join(ROOT, "oracle"))
 from paper_2002_00054_amd import synth  # noqa: E402  (seeded inputs only)
 import oracle  # noqa: E402
 
-OUT = os.path.join(ROOT, "paper_2002_00054_amd", "data", "ni_scaling.json")
+DATA = os.path.join(ROOT, "paper_2002_00054_amd", "data")
 
 
-def main():
-    table = synth.ni_sf_table()  # shift 0, scale 1: raw G
+def write(table, name, what):
     pot = oracle.Potential(table, synth.ni_nets(), n_el=1)
     b = synth.fcc_box(4, 0)
     G = pot.descriptors(b.pos, b.types, b.box)[:, :pot.n_sf[0]]
     rng = G.max(axis=0) - G.min(axis=0)
     doc = {
-        "what": "frozen shift (mean) and scale (max-min) of raw SFs, Ni table, "
+        "what": f"frozen shift (mean) and scale (max-min) of raw SFs, {what}, "
                 "256-atom fcc box 4 cells per axis seed 0, FP64 oracle",
         "shift": {"Ni": [float(x) for x in G.mean(axis=0)]},
         "scale": {"Ni": [float(x) for x in np.where(rng < 1e-12, 1.0, rng)]},
     }
-    with open(OUT, "w") as f:
+    out = os.path.join(DATA, name)
+    with open(out, "w") as f:
         json.dump(doc, f, indent=1)
-    print("wrote", OUT)
+    print("wrote", out)
+
+
+def main():
+    # shift 0, scale 1 in the tables: raw G
+    write(synth.ni_sf_table(), "ni_scaling.json", "Ni table")
+    write(synth.ni_g9_sf_table(), "ni_g9_scaling.json", "Ni table with wide angular SFs")
 
 
 if __name__ == "__main__":

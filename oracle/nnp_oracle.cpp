@@ -12,7 +12,9 @@
 //           angular G3 over pairs of neighbours (the "extra loop over
 //           neighbors of neighbors"; the paper does not print it, so the
 //           narrow angular function of Behler, the paper's ref. [18], is
-//           used);
+//           used); also its wide variant G9 (no r_jk factor: every pair of
+//           neighbours within the cutoff of i counts), the other angular
+//           function of that family;
 //   step 2  E_i = NN_{e_i}(G_i), one network per element (Fig. 1(c));
 //           E = sum_i E_i;
 //   step 3  forces f = -dE/dr (sign convention of Fig. 1(a)/(b)), by the
@@ -41,7 +43,7 @@ typedef struct {
   int n_el;
   int n_sf;                 // table entries over all centre elements
   const int* centre;        // [n_sf] centre element
-  const int* kind;          // [n_sf] 2 = radial G2, 3 = narrow angular G3
+  const int* kind;          // [n_sf] 2 = radial G2, 3 = narrow angular G3, 9 = wide angular G9
   const int* nbr0;          // [n_sf] neighbour element (G2) / first of pair (G3)
   const int* nbr1;          // [n_sf] second of pair (G3), ignored for G2
   const double* eta;        // [n_sf] A^-2
@@ -252,13 +254,19 @@ void descriptors(const Pot& P, int64_t i, const std::vector<int64_t>& nb, const 
       const double cth = dot3(u, v) / (ra * rb);
       for (int s = 0; s < ns; ++s) {
         const SFDef& d = S[s];
-        if (d.kind != 3) continue;
+        if (d.kind != 3 && d.kind != 9) continue;
         const bool match = (d.n0 == ej && d.n1 == ek) || (d.n0 == ek && d.n1 == ej);
-        if (!match || ra >= d.rc || rb >= d.rc || rd >= d.rc) continue;
+        if (!match || ra >= d.rc || rb >= d.rc) continue;
         const int z = (int)d.zeta;
-        G[s] += std::pow(2.0, 1.0 - d.zeta) * ipow(1.0 + d.lam * cth, z) *
-                std::exp(-d.eta * (ra * ra + rb * rb + rd * rd)) * fcut(ra, d.rc) * fcut(rb, d.rc) *
-                fcut(rd, d.rc);
+        const double ang = std::pow(2.0, 1.0 - d.zeta) * ipow(1.0 + d.lam * cth, z);
+        if (d.kind == 3) {
+          if (rd >= d.rc) continue;
+          G[s] += ang * std::exp(-d.eta * (ra * ra + rb * rb + rd * rd)) * fcut(ra, d.rc) * fcut(rb, d.rc) *
+                  fcut(rd, d.rc);
+        } else {
+          // G9 = 2^(1-zeta) sum_{j<k} (1 + lam cos)^zeta exp(-eta (r_ij^2 + r_ik^2)) f_c(r_ij) f_c(r_ik)
+          G[s] += ang * std::exp(-d.eta * (ra * ra + rb * rb)) * fcut(ra, d.rc) * fcut(rb, d.rc);
+        }
       }
     }
   }
@@ -351,20 +359,24 @@ void descriptor_gradients(const Pot& P, int64_t i, const std::vector<int64_t>& n
       }
       for (int s = 0; s < ns; ++s) {
         const SFDef& d = S[s];
-        if (d.kind != 3) continue;
+        if (d.kind != 3 && d.kind != 9) continue;
         const bool match = (d.n0 == ej && d.n1 == ek) || (d.n0 == ek && d.n1 == ej);
-        if (!match || ra >= d.rc || rb >= d.rc || rd >= d.rc) continue;
+        if (!match || ra >= d.rc || rb >= d.rc) continue;
+        const bool wide = d.kind == 9;  // G9: no r_jk factor, no r_jk cutoff
+        if (!wide && rd >= d.rc) continue;
         const int z = (int)d.zeta;
         const double pre = std::pow(2.0, 1.0 - d.zeta);
         const double Pb = 1.0 + d.lam * cth;
-        const double X = std::exp(-d.eta * (ra * ra + rb * rb + rd * rd));
-        const double fa = fcut(ra, d.rc), fb = fcut(rb, d.rc), fd = fcut(rd, d.rc);
-        const double dfa = dfcut(ra, d.rc), dfb = dfcut(rb, d.rc), dfd = dfcut(rd, d.rc);
+        const double X = std::exp(-d.eta * (ra * ra + rb * rb + (wide ? 0.0 : rd * rd)));
+        const double fa = fcut(ra, d.rc), fb = fcut(rb, d.rc), fd = wide ? 1.0 : fcut(rd, d.rc);
+        const double dfa = dfcut(ra, d.rc), dfb = dfcut(rb, d.rc);
+        // wide: T does not depend on r_jk, so dT/dd = 0 (fd = 1, dfd = 0, no eta d^2 term)
+        const double dfd = wide ? 0.0 : dfcut(rd, d.rc) - 2.0 * d.eta * rd * fd;
         const double Pz = ipow(Pb, z);
         const double dT_dc = pre * z * d.lam * ipow(Pb, z - 1) * X * fa * fb * fd;
         const double dT_da = pre * Pz * X * (-2.0 * d.eta * ra * fa + dfa) * fb * fd;
         const double dT_db = pre * Pz * X * fa * (-2.0 * d.eta * rb * fb + dfb) * fd;
-        const double dT_dd = pre * Pz * X * fa * fb * (-2.0 * d.eta * rd * fd + dfd);
+        const double dT_dd = pre * Pz * X * fa * fb * dfd;
         double gi[3], gj[3], gk[3];
         for (int c = 0; c < 3; ++c) {
           // a depends on r_i, r_j; b on r_i, r_k; d on r_j, r_k; cos on all three.

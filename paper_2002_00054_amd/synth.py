@@ -173,7 +173,8 @@ class SF:
     """One symmetry function of one centre element.
 
     kind 2: radial, neighbour element ``nbr[0]``;
-    kind 3: narrow angular, unordered neighbour-element pair ``nbr``.
+    kind 3: narrow angular, unordered neighbour-element pair ``nbr``;
+    kind 9: wide angular (no r_jk factor), unordered pair ``nbr``.
     ``shift``/``scale`` are the frozen centring/scaling constants
     (G_scaled = (G - shift) / scale); 0/1 until set.
     """
@@ -387,18 +388,27 @@ def ni_sf_table() -> list[SF]:
     return table
 
 
+def ni_g9_sf_table() -> list[SF]:
+    """The wide variant of the Ni table: the same 8 radial SFs, then the 6
+    angular ones as wide functions G9 (kind 9: no r_jk factor or cutoff)."""
+    table = [SF(0, 2, (0,), eta, rc=NI_RCUT) for eta in NI_RADIAL_ETAS]
+    table += [SF(0, 9, (0, 0), eta, 0.0, float(zeta), lam, rc=NI_RCUT) for eta, zeta, lam in NI_ANGULAR]
+    return table
+
+
 def ni_nets(seed: int = 2000) -> list[Net]:
     return xavier_nets(sf_counts(ni_sf_table(), n_el=1), seed)
 
 
-def ni_table_scaled(path: str | None = None) -> list[SF]:
-    """``ni_sf_table`` with the stored shift/scale filled in."""
+def ni_table_scaled(path: str | None = None, wide: bool = False) -> list[SF]:
+    """``ni_sf_table`` (or, with ``wide``, ``ni_g9_sf_table``) with the stored
+    shift/scale filled in."""
     import os
 
     if path is None:
-        path = os.path.join(os.path.dirname(__file__), "data", "ni_scaling.json")
+        path = os.path.join(os.path.dirname(__file__), "data", "ni_g9_scaling.json" if wide else "ni_scaling.json")
     sc = load_scaling(path)
-    table = ni_sf_table()
+    table = ni_g9_sf_table() if wide else ni_sf_table()
     for k, s in enumerate(table):
         s.shift = float(sc["shift"]["Ni"][k])
         s.scale = float(sc["scale"]["Ni"][k])
