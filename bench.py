@@ -103,7 +103,8 @@ def cpu_baseline(table, nets, budget_s=12.0, nthreads=0, workload="water"):
 def report(table, nets):
     """Extra JSON lines instead of the contract line: the measured device peaks,
     every form over the size sweep, the single-element fcc workload (3.9 A
-    cutoff, up to 1,492,992 atoms), the training step of the differentiation
+    cutoff, up to 1,492,992 atoms; narrow and wide angular SFs), the two
+    levels of parallelism, the training step of the differentiation
     form (32 uneven boxes, loss = energy MSE + 0.1 force MSE, synthetic
     targets) with recomputed and with stored SF derivatives, the forward with
     each, velocity Verlet MD steps (throughput and energy drift), and the CPU
@@ -149,6 +150,19 @@ def report(table, nets):
             print(json.dumps(line), flush=True)
             del x, t
         pot.close()
+        torch.cuda.empty_cache()
+    # the fcc workload with wide angular functions G9 (thread-per-centre passes)
+    g9_table = synth.ni_table_scaled(wide=True)
+    bb = synth.fcc_box(72, 72)
+    for form in ("fp32", "fp64"):
+        pot = Potential(g9_table, ni_nets, precision=form, elements=("Ni",))
+        x = torch.tensor(bb.pos, dtype=pot.dtype, device=dev)
+        t = torch.tensor(bb.types, dtype=torch.int32, device=dev)
+        ms, st = time_form(pot, x, t, bb.box, 5, 1)
+        print(json.dumps({"report": "ni_g9", "form": form, "atoms": bb.n_atoms, "ms_per_step": ms,
+                          "atom_steps_per_s": bb.n_atoms / (ms * 1e-3), "stages_ms": st}), flush=True)
+        pot.close()
+        del x, t
         torch.cuda.empty_cache()
     # level of parallelism of the SF and force passes: a wave per centre against a thread per centre
     for wl, bb, tb, nt in (("ni", synth.fcc_box(72, 72), ni_table, ni_nets),

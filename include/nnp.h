@@ -12,6 +12,9 @@
  *             G2 = sum_j exp(-eta (r_ij - rs)^2) fc(r_ij)
  *             G3 = 2^(1-zeta) sum_{j<k} (1 + lambda cos theta_ijk)^zeta
  *                  exp(-eta (r_ij^2 + r_ik^2 + r_jk^2)) fc(r_ij) fc(r_ik) fc(r_jk)
+ *           and its wide variant of the same family, without the r_jk factor
+ *             G9 = 2^(1-zeta) sum_{j<k} (1 + lambda cos theta_ijk)^zeta
+ *                  exp(-eta (r_ij^2 + r_ik^2)) fc(r_ij) fc(r_ik)
  *           with fc(r) = (cos(pi r / rc) + 1) / 2 for r < rc, else 0;
  *   step 2  E_i = NN_{e_i}((G_i - shift) / scale), one feed-forward network per
  *           element (Fig. 1(c)), tanh hidden layers, linear output;
@@ -65,11 +68,14 @@ typedef enum { NNP_FP64 = 0, NNP_FP32 = 1, NNP_BF16_MIXED = 2 } nnp_precision;
 /* One symmetry function of the table (Sec. 3.1 step 1).
  *  centre    element of the centre atom, in [0, n_el)
  *  kind      2 = radial G2 (neighbour element nbr[0]);
- *            3 = narrow angular G3 (unordered neighbour-element pair nbr[0], nbr[1])
+ *            3 = narrow angular G3 (unordered neighbour-element pair nbr[0], nbr[1]);
+ *            9 = wide angular G9 (same pair convention).  A table holding any
+ *                G9 runs its SF and force passes one thread per centre, and
+ *                nnp_backward and NNP_DERIV_STORED then return NNP_E_STATE.
  *  eta       Gaussian exponent, A^-2, >= 0
- *  rs        radial shift, A (G2 only; must be 0 for G3)
- *  zeta      exponent, one of 1, 2, 4, 8, 16, 32 (G3 only)
- *  lambda    +1 or -1 (G3 only)
+ *  rs        radial shift, A (G2 only; must be 0 for G3 and G9)
+ *  zeta      exponent, one of 1, 2, 4, 8, 16, 32 (G3 and G9 only)
+ *  lambda    +1 or -1 (G3 and G9 only)
  *  rc        cutoff radius, A; every entry of one table must use the same rc
  *  shift, scale  centring/scaling: the network sees (G - shift) / scale, scale != 0
  * The order of the entries of one centre element is the order of that

@@ -60,6 +60,7 @@ struct nnp_handle {
   // stored-Jacobian differentiation form: the last forward's inputs, for
   // reuse of its J store by nnp_backward
   int parallelism = NNP_PAR_AUTO;        // SF and force passes: wave or thread per centre
+  bool has_wide = false;                 // the table holds wide angular SFs (thread-per-centre passes only)
   int deriv_mode = NNP_DERIV_RECOMPUTE;
   bool jac_valid = false;
   int jac_cap = 0;
@@ -168,6 +169,7 @@ DevTab<T> convert_tab(const DevTab<double>& s) {
         t.ang_bit[e][c][k] = s.ang_bit[e][c][k];
         t.ang_pre[e][c][k] = (T)s.ang_pre[e][c][k];
         t.ang_out[e][c][k] = s.ang_out[e][c][k];
+        t.ang_wide[e][c][k] = s.ang_wide[e][c][k];
       }
     }
     for (int c = 0; c < MAX_CLS; ++c)
@@ -443,7 +445,7 @@ int check_flags(nnp_handle* h, hipStream_t stream, Common& cm, nnp_status* st) {
 
 // Thread per centre for the SF and force passes only when asked for: a wave
 // per centre was measured faster on both workloads, short rows included.
-bool flat_passes(const nnp_handle* h) { return h->parallelism == NNP_PAR_THREAD; }
+bool flat_passes(const nnp_handle* h) { return h->parallelism == NNP_PAR_THREAD || h->has_wide; }
 
 // The stored-Jacobian form applies to the FP64 and FP32 handles.
 template <int P>
@@ -636,6 +638,7 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
   const int64_t n = cm.B.n;
   if (n > 0 && (!pos_v || !types)) return fail(h, NNP_E_ARG, "pos and types must not be NULL");
   if (!grad) return fail(h, NNP_E_ARG, "grad_params must not be NULL");
+  if (h->has_wide) return fail(h, NNP_E_STATE, "nnp_backward does not support wide angular SFs (kind 9)");
   const IO* pos = reinterpret_cast<const IO*>(pos_v);
   const IO* dLdF = reinterpret_cast<const IO*>(dL_dF_v);
   h->cap = initial_cap(h, cm.B);
@@ -807,9 +810,9 @@ nnp_status build_table(nnp_handle* h, int n_el, int n_sf, const nnp_sf* sf, cons
     const nnp_sf& d = sf[s];
     const std::string at = "sf[" + std::to_string(s) + "]: ";
     if (d.centre < 0 || d.centre >= n_el) return fail(nullptr, NNP_E_ARG, at + "centre out of range");
-    if (d.kind != 2 && d.kind != 3) return fail(nullptr, NNP_E_ARG, at + "kind must be 2 or 3");
+    if (d.kind != 2 && d.kind != 3 && d.kind != 9) return fail(nullptr, NNP_E_ARG, at + "kind must be 2, 3 or 9");
     if (d.nbr[0] < 0 || d.nbr[0] >= n_el) return fail(nullptr, NNP_E_ARG, at + "nbr[0] out of range");
-    if (d.kind == 3 && (d.nbr[1] < 0 || d.nbr[1] >= n_el)) return fail(nullptr, NNP_E_ARG, at + "nbr[1] out of range");
+    if (d.kind != 2 && (d.nbr[1] < 0 || d.nbr[1] >= n_el)) return fail(nullptr, NNP_E_ARG, at + "nbr[1] out of range");
     if (!std::isfinite(d.eta) || d.eta < 0) return fail(nullptr, NNP_E_ARG, at + "eta must be finite and >= 0");
     if (!std::isfinite(d.rc) || d.rc <= 0) return fail(nullptr, NNP_E_ARG, at + "rc must be > 0");
     if (h->rc == 0.0) h->rc = d.rc;
@@ -850,12 +853,17 @@ nnp_status build_table(nnp_handle* h, int n_el, int n_sf, const nnp_sf* sf, cons
         etas[e].push_back(d.eta);
       }
       const int qb = (d.lambda > 0 ? 0 : 6) + kz;
-      if (t.qn_out[e][cls][qb * MAX_NE + ei] >= 0)
-        return fail(nullptr, NNP_E_ARG, at + "duplicate angular SF (same class, eta, zeta and lambda)");
-      t.qn_out[e][cls][qb * MAX_NE + ei] = k;
-      t.qn_pre[e][cls][qb * MAX_NE + ei] = std::pow(2.0, 1.0 - d.zeta);
+      if (d.kind == 3) {  // the (q, n) slot map of the wave kernels covers the narrow functions
+        if (t.qn_out[e][cls][qb * MAX_NE + ei] >= 0)
+          return fail(nullptr, NNP_E_ARG, at + "duplicate angular SF (same class, eta, zeta and lambda)");
+        t.qn_out[e][cls][qb * MAX_NE + ei] = k;
+        t.qn_pre[e][cls][qb * MAX_NE + ei] = std::pow(2.0, 1.0 - d.zeta);
+        qn_mask |= qn_bit(qb, ei);
+      } else {
+        t.ang_wide[e][cls][q] = 1;
+        h->has_wide = true;
+      }
       t.ang_bit[e][cls][q] = qb * MAX_NE + ei;
-      qn_mask |= qn_bit(qb, ei);
       t.ang_pre[e][cls][q] = std::pow(2.0, 1.0 - d.zeta);
       t.ang_out[e][cls][q] = k;
     }
@@ -1133,6 +1141,8 @@ nnp_status nnp_set_derivative_mode(nnp_handle* h, int mode) {
     return fail(h, NNP_E_ARG, "derivative mode must be NNP_DERIV_RECOMPUTE or NNP_DERIV_STORED");
   if (mode == NNP_DERIV_STORED && h->prec == NNP_BF16_MIXED)
     return fail(h, NNP_E_STATE, "the stored-Jacobian mode needs an NNP_FP64 or NNP_FP32 handle");
+  if (mode == NNP_DERIV_STORED && h->has_wide)
+    return fail(h, NNP_E_STATE, "the stored-Jacobian mode does not support wide angular SFs (kind 9)");
   if (mode != h->deriv_mode) h->jac_valid = false;
   h->deriv_mode = mode;
   return NNP_OK;

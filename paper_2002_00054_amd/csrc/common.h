@@ -72,6 +72,7 @@ struct DevTab {
   int ang_bit[MAX_EL][MAX_CLS][MAX_ANG];
   T ang_pre[MAX_EL][MAX_CLS][MAX_ANG];     // 2^(1 - zeta)
   int ang_out[MAX_EL][MAX_CLS][MAX_ANG];
+  int ang_wide[MAX_EL][MAX_CLS][MAX_ANG];  // 1: wide function (no r_jk factor or cutoff)
   // the same as a map from (q, n) to the one SF of the class using it (-1: none)
   int qn_out[MAX_EL][MAX_CLS][12 * MAX_NE];
   T qn_pre[MAX_EL][MAX_CLS][12 * MAX_NE];

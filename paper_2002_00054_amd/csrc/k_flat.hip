@@ -1,6 +1,7 @@
 // Flat parallelism: one thread per centre atom, the paper's "flat" level
 // (threads over atoms only, Sec. 4.3), kept to compare the levels of
-// parallelism.  Every lane is a centre and walks its own neighbours and
+// parallelism, and the path of tables with wide angular functions G9 (the
+// narrow function without its r_jk factor and cutoff: every pair counts).  Every lane is a centre and walks its own neighbours and
 // pairs; a wave per centre (k_triplet) was measured faster on both workloads,
 // short neighbour rows included, because here each lane reads its own row
 // (64 rows per load instruction) and the pair loop diverges.
@@ -27,14 +28,20 @@ constexpr int FLAT = 64;  // threads (centres) per workgroup: one wave
 template <class T>
 struct AngClass {
   int na;
+  bool any_narrow, any_wide;
+  bool wide[MAX_ANG];  // wide function: no r_jk factor or cutoff
   int out[MAX_ANG];
   int ni[MAX_ANG];   // index of the SF's exponent among the centre's distinct ones
   int zl[MAX_ANG];   // log2 zeta
   T pre[MAX_ANG], lam[MAX_ANG], zeta[MAX_ANG], eta[MAX_ANG];
   __device__ inline void load(const DevTab<T>* tab, int ec, int cls) {
     na = tab->ang_cnt[ec][cls];
+    any_narrow = any_wide = false;
 #pragma unroll
     for (int q = 0; q < MAX_ANG; ++q) {
+      wide[q] = q < na && tab->ang_wide[ec][cls][q] != 0;
+      any_wide |= wide[q];
+      any_narrow |= q < na && !wide[q];
       const int bit = q < na ? tab->ang_bit[ec][cls][q] : 0;
       const int qb = bit / MAX_NE;
       ni[q] = bit % MAX_NE;
@@ -135,20 +142,25 @@ __global__ void __launch_bounds__(FLAT) k_flat_sf(TripArgs<P> a) {
           const V4 B = row[k];
           const T dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
           const T d2 = dx * dx + dy * dy + dz * dz;
-          if (!(d2 < rc2)) continue;
+          const bool near = d2 < rc2;
+          if (!(near || cl.any_wide)) continue;
           const T b2 = B.x * B.x + B.y * B.y + B.z * B.z;
           const T cs = (A.x * B.x + A.y * B.y + A.z * B.z) * ia * rsqrt_t(b2);
-          const T f3 = fca * cut.value(b2) * cut.value_in(d2);
-          const T s2 = a2 + b2 + d2;
-          T ex[MAX_NE];
+          const T f2 = fca * cut.value(b2);
+          const T f3 = near ? f2 * cut.value_in(d2) : T(0);
+          T ex[MAX_NE], exw[MAX_NE];  // e^{-eta (a^2 + b^2 + d^2)} (narrow), e^{-eta (a^2 + b^2)} (wide)
 #pragma unroll
-          for (int n = 0; n < MAX_NE; ++n) ex[n] = n < ne ? exp_scaled(-eta_n[n] * s2, -eta_n[n] * s2 * T(1.4426950408889634)) : T(0);
+          for (int n = 0; n < MAX_NE; ++n) {
+            const T sn = a2 + b2 + d2, sw = a2 + b2;
+            ex[n] = n < ne && near && cl.any_narrow ? exp_scaled(-eta_n[n] * sn, -eta_n[n] * sn * T(1.4426950408889634)) : T(0);
+            exw[n] = n < ne && cl.any_wide ? exp_scaled(-eta_n[n] * sw, -eta_n[n] * sw * T(1.4426950408889634)) : T(0);
+          }
 #pragma unroll
           for (int q = 0; q < MAX_ANG; ++q) {
             if (q < cl.na) {
               T pz, pz1;
               powers(T(1) + cl.lam[q] * cs, cl.zl[q], pz, pz1);
-              gq[q] += (Acc)(pz * pick(ex, cl.ni[q]) * f3);
+              gq[q] += (Acc)(cl.wide[q] ? pz * pick(exw, cl.ni[q]) * f2 : pz * pick(ex, cl.ni[q]) * f3);
             }
           }
         }
@@ -225,35 +237,47 @@ __global__ void __launch_bounds__(FLAT) k_flat_force(TripArgs<P> a) {
           const V4 B = row[k];
           const T dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
           const T d2 = dx * dx + dy * dy + dz * dz;
-          if (!(k != j && d2 < rc2)) continue;
+          const bool near = d2 < rc2;
+          if (!(k != j && (near || cl.any_wide))) continue;
           const T b2 = B.x * B.x + B.y * B.y + B.z * B.z;
           const T ib = rsqrt_t(b2);
           const T iab = ia * ib;
           const T cs = (A.x * B.x + A.y * B.y + A.z * B.z) * iab;
           const T fcb = cut.value(b2);
-          T fcd, dfcd;
-          cut.eval_in(d2, fcd, dfcd);
-          const T s2 = a2 + b2 + d2;
-          T ex[MAX_NE];
+          T fcd = T(0), dfcd = T(0);
+          if (near) cut.eval_in(d2, fcd, dfcd);
+          T ex[MAX_NE], exw[MAX_NE];  // e^{-eta (a^2 + b^2 + d^2)} (narrow), e^{-eta (a^2 + b^2)} (wide)
 #pragma unroll
-          for (int n = 0; n < MAX_NE; ++n) ex[n] = n < ne ? exp_scaled(-eta_n[n] * s2, -eta_n[n] * s2 * T(1.4426950408889634)) : T(0);
-          // Uc = sum_q w zeta lam pz1 E, Uz = sum_q w pz E, Ue = sum_q w eta pz E
-          T Uc = T(0), Uz = T(0), Ue = T(0);
+          for (int n = 0; n < MAX_NE; ++n) {
+            const T sn = a2 + b2 + d2, sw = a2 + b2;
+            ex[n] = n < ne && near && cl.any_narrow ? exp_scaled(-eta_n[n] * sn, -eta_n[n] * sn * T(1.4426950408889634)) : T(0);
+            exw[n] = n < ne && cl.any_wide ? exp_scaled(-eta_n[n] * sw, -eta_n[n] * sw * T(1.4426950408889634)) : T(0);
+          }
+          // narrow (n) and wide (w) sums: Uc = sum_q w zeta lam pz1 E, Uz = sum_q w pz E, Ue = sum_q w eta pz E
+          T Ucn = T(0), Uzn = T(0), Uen = T(0), Ucw = T(0), Uzw = T(0), Uew = T(0);
 #pragma unroll
           for (int q = 0; q < MAX_ANG; ++q) {
             if (q < cl.na) {
               T pz, pz1;
               powers(T(1) + cl.lam[q] * cs, cl.zl[q], pz, pz1);
-              const T we = w[q] * pick(ex, cl.ni[q]);
-              Uc += we * cl.zeta[q] * cl.lam[q] * pz1;
-              Uz += we * pz;
-              Ue += we * cl.eta[q] * pz;
+              const T we = w[q] * (cl.wide[q] ? pick(exw, cl.ni[q]) : pick(ex, cl.ni[q]));
+              const T c1 = we * cl.zeta[q] * cl.lam[q] * pz1, c2 = we * pz, c3 = we * cl.eta[q] * pz;
+              if (cl.wide[q]) {
+                Ucw += c1;
+                Uzw += c2;
+                Uew += c3;
+              } else {
+                Ucn += c1;
+                Uzn += c2;
+                Uen += c3;
+              }
             }
           }
-          const T f3 = fca * fcb * fcd;
-          const T tc = Uc * f3;                                   // dT/dcos
-          const T ta = T(2) * (Uz * dfca * fcb * fcd - Ue * f3);  // 2 dT/d(a^2)
-          const T td = T(2) * (Uz * fca * fcb * dfcd - Ue * f3);  // 2 dT/d(d^2)
+          const T f2 = fca * fcb;
+          const T f3 = f2 * fcd;
+          const T tc = Ucn * f3 + Ucw * f2;                                                     // dT/dcos
+          const T ta = T(2) * (Uzn * dfca * fcb * fcd - Uen * f3 + Uzw * dfca * fcb - Uew * f2);  // 2 dT/d(a^2)
+          const T td = T(2) * (Uzn * fca * fcb * dfcd - Uen * f3);                               // 2 dT/d(d^2)
           const T ca = cs * inv_a2;
           gx += tc * (B.x * iab - ca * A.x) + ta * A.x - td * dx;
           gy += tc * (B.y * iab - ca * A.y) + ta * A.y - td * dy;

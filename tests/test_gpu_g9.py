@@ -1,0 +1,105 @@
+"""Wide angular functions G9 (kind 9) through the C ABI, against the FP64
+oracle at the usual bars: the fcc workload with its angular SFs made wide
+(up to the 1,492,992-atom box, sampled atoms there), and a two-element water
+table mixing narrow and wide functions in every neighbour class.  Tables
+with G9 run the thread-per-centre passes; the paths that do not support them
+report NNP_E_STATE."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import check_fp32, check_fp64, make_potential, oracle_input, run, say
+from paper_2002_00054_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _ni():
+    table, nets = synth.ni_table_scaled(wide=True), synth.ni_nets()
+    return table, nets, oracle.Potential(table, nets, n_el=1)
+
+
+def _water_mixed():
+    H, O = synth.H, synth.O
+    table = []
+    for c in (H, O):
+        for nb in (H, O):
+            table += [synth.SF(c, 2, (nb,), eta) for eta in synth.RADIAL_ETAS]
+        for cls in synth.PAIR_CLASSES:
+            for kind in (3, 9):
+                table += [synth.SF(c, kind, cls, 0.001, 0.0, 1.0, -1.0), synth.SF(c, kind, cls, 0.03, 0.0, 4.0, 1.0)]
+    nets = synth.xavier_nets(synth.sf_counts(table), 11)
+    # frozen centring/scaling from the oracle's SFs of the 192-atom box (as for
+    # the water table): wide sums over ~3,600 pairs reach the thousands raw
+    b = synth.water_box(4, 0)
+    G = oracle.Potential(table, nets).descriptors(b.pos, b.types, b.box)
+    k = {H: 0, O: 0}
+    for sf in table:
+        g = G[b.types == sf.centre, k[sf.centre]]
+        rng = float(g.max() - g.min())
+        sf.shift, sf.scale = float(g.mean()), rng if rng >= 1e-12 else 1.0
+        k[sf.centre] += 1
+    return table, nets, oracle.Potential(table, nets)
+
+
+def _check(form, ei, f, ref):
+    if form == "fp64":
+        check_fp64(ei, f, ref["Ei"], ref["F"])
+    elif form == "fp32":
+        check_fp32(ei, f, ref["Ei"], ref["F"])
+    else:
+        assert float(np.sqrt(np.mean((f - ref["F"]) ** 2))) <= 5e-3
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("n,seed", [(3, 1), (8, 2), (20, 3)])
+def test_fcc_g9(form, n, seed):
+    table, nets, ref_pot = _ni()
+    b = synth.fcc_box(n, seed)
+    say("g9 fcc", form, b.n_atoms)
+    pot = make_potential(form, table, nets)
+    e, ei, f = run(pot, b)
+    _check(form, ei, f, ref_pot.compute(oracle_input(b, form), b.types, b.box, use_cells=True))
+    pot.close()
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("side,seed", [(4, 2), (16, 12)])
+def test_water_mixed_narrow_wide(form, side, seed):
+    table, nets, ref_pot = _water_mixed()
+    b = synth.water_box(side, seed)
+    say("g9 water mixed", form, b.n_atoms)
+    pot = make_potential(form, table, nets)
+    e, ei, f = run(pot, b)
+    _check(form, ei, f, ref_pot.compute(oracle_input(b, form), b.types, b.box, use_cells=True))
+    pot.close()
+
+
+def test_fcc_g9_fullsize_sampled():
+    table, nets, ref_pot = _ni()
+    b = synth.fcc_box(72, 72)
+    rng = np.random.default_rng(9)
+    idx = np.array(sorted(set(rng.choice(b.n_atoms, size=100, replace=False).tolist())), dtype=np.int64)
+    pot = make_potential("fp32", table, nets)
+    e, ei, f = run(pot, b)
+    Ei, F = ref_pot.sampled(oracle_input(b, "fp32"), b.types, b.box, idx)
+    check_fp32(ei[idx], f[idx], Ei, F)
+    assert np.max(np.abs(np.sum(f, axis=0))) < 0.05
+    pot.close()
+
+
+def test_unsupported_paths_report_state_error():
+    import torch
+
+    from paper_2002_00054_amd.nnp import NNPError
+
+    table, nets, _ = _ni()
+    pot = make_potential("fp64", table, nets)
+    with pytest.raises(NNPError, match="NNP_E_STATE"):
+        pot.set_derivative_mode("stored")
+    b = synth.fcc_box(3, 1)
+    pos = torch.tensor(b.pos, dtype=torch.float64, device="cuda")
+    types = torch.tensor(b.types, dtype=torch.int32, device="cuda")
+    with pytest.raises(NNPError, match="NNP_E_STATE"):
+        pot.backward(pos, types, [0, b.n_atoms], b.box[None])
+    pot.close()
