@@ -70,8 +70,8 @@ typedef enum { NNP_FP64 = 0, NNP_FP32 = 1, NNP_BF16_MIXED = 2 } nnp_precision;
  *  kind      2 = radial G2 (neighbour element nbr[0]);
  *            3 = narrow angular G3 (unordered neighbour-element pair nbr[0], nbr[1]);
  *            9 = wide angular G9 (same pair convention).  A table holding any
- *                G9 runs its SF and force passes one thread per centre, and
- *                nnp_backward and NNP_DERIV_STORED then return NNP_E_STATE.
+ *                G9 runs its SF, force and force-adjoint passes one thread per
+ *                centre; NNP_DERIV_STORED then returns NNP_E_STATE.
  *  eta       Gaussian exponent, A^-2, >= 0
  *  rs        radial shift, A (G2 only; must be 0 for G3 and G9)
  *  zeta      exponent, one of 1, 2, 4, 8, 16, 32 (G3 and G9 only)
@@ -203,8 +203,8 @@ nnp_status nnp_md_run(nnp_handle* h, int64_t n_atoms, void* pos, void* vel, void
  *                  pairs alone (the paper's flat level); kept for comparison.
  *  NNP_PAR_AUTO    (default) the faster level; on this device that is a
  *                  wave per centre for long and short neighbour rows alike.
- * Both give the same results up to rounding order.  The force-adjoint pass of
- * nnp_backward always runs wave per centre.  An unknown mode is NNP_E_ARG.
+ * Both give the same results up to rounding order; the force-adjoint pass of
+ * nnp_backward follows the same choice.  An unknown mode is NNP_E_ARG.
  */
 typedef enum { NNP_PAR_AUTO = 0, NNP_PAR_WAVE = 1, NNP_PAR_THREAD = 2 } nnp_parallelism;
 nnp_status nnp_set_parallelism(nnp_handle* h, int mode);

@@ -638,7 +638,6 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
   const int64_t n = cm.B.n;
   if (n > 0 && (!pos_v || !types)) return fail(h, NNP_E_ARG, "pos and types must not be NULL");
   if (!grad) return fail(h, NNP_E_ARG, "grad_params must not be NULL");
-  if (h->has_wide) return fail(h, NNP_E_STATE, "nnp_backward does not support wide angular SFs (kind 9)");
   const IO* pos = reinterpret_cast<const IO*>(pos_v);
   const IO* dLdF = reinterpret_cast<const IO*>(dL_dF_v);
   h->cap = initial_cap(h, cm.B);
@@ -690,8 +689,9 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
     }
     if (!stored) {
       TripArgs<P> ta = trip_args<P>(h, cm);
-      if (std::max(triplet_lds_bytes<P>(0, h->variant, h->lcap), triplet_lds_bytes<P>(2, h->variant, h->lcap)) >
-          lds_limit())
+      if (!flat_passes(h) &&
+          std::max(triplet_lds_bytes<P>(0, h->variant, h->lcap), triplet_lds_bytes<P>(2, h->variant, h->lcap)) >
+              lds_limit())
         return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) +
                                       " neighbours needs more LDS per workgroup than the device allows");
       ta.G = G;
@@ -717,7 +717,8 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
     TripArgs<P> ta = trip_args<P>(h, cm);
     ta.delta = delta;
     ta.V = V;
-    launch_triplet<P>(2, h->variant, ta, stream);
+    if (flat_passes(h)) launch_flat<P>(2, ta, stream);
+    else launch_triplet<P>(2, h->variant, ta, stream);
   }
   mk.mark("jvp");
   launch_gather_struct_grad(n, cm.bin.perm, cm.d_soff, n_struct, dL_dE, gE_atom, stream);

@@ -298,6 +298,123 @@ __global__ void __launch_bounds__(FLAT) k_flat_force(TripArgs<P> a) {
   atomic_add(&a.F[3 * c + 2], (FAcc)fiz);
 }
 
+// Force-adjoint product of the differentiation form, one thread per centre:
+// v_is = sum_m delta_m . dG_is/dr_m = sum_j (delta_j - delta_i) . dG_is/dr_j,
+// with the same ordered-pair walk as the force pass (every visit adds the
+// r_j gradient of each SF of the pair, projected on delta_j - delta_i).
+template <int P>
+__global__ void __launch_bounds__(FLAT) k_flat_jvp(TripArgs<P> a) {
+  using T = typename Types<P>::T;
+  using Acc = typename Types<P>::Acc;
+  using IO = typename Types<P>::IO;
+  using V4 = typename Vec4<T>::type;
+  __shared__ Acc vs[LD][FLAT];
+  const int lane = threadIdx.x;
+  const int64_t c = xcd_remap(blockIdx.x, gridDim.x) * FLAT + lane;
+  if (c >= a.n) return;  // no workgroup barrier below
+  const DevTab<T>* __restrict__ tab = a.tab;
+  Cutoff<T> cut;
+  cut.load(tab);
+  const T rc2 = tab->rc2;
+  const int n_el = tab->n_el;
+  const int ec = elem_of(a.pos4[c].w);
+  const int ne = tab->n_eta[ec];
+  Rows rw;
+  rw.load(a.nnb[c], n_el);
+  const V4* __restrict__ row = a.nbr + c * (int64_t)a.cap;
+#pragma unroll
+  for (int s = 0; s < LD; ++s) vs[s][lane] = Acc(0);
+  const T di0 = (T)a.delta[3 * c + 0], di1 = (T)a.delta[3 * c + 1], di2 = (T)a.delta[3 * c + 2];
+  T eta_n[MAX_NE];
+#pragma unroll
+  for (int n = 0; n < MAX_NE; ++n) eta_n[n] = n < ne ? tab->aeta[ec][n] : T(0);
+
+  for (int f = 0; f < n_el; ++f) {
+    const int nr = tab->rad_cnt[ec][f];
+    for (int j = rw.lo(f); j < rw.lo(f + 1); ++j) {
+      const V4 A = row[j];
+      const int64_t jj = entry_index(A);
+      const T d0 = (T)a.delta[3 * jj + 0] - di0, d1 = (T)a.delta[3 * jj + 1] - di1, d2j = (T)a.delta[3 * jj + 2] - di2;
+      const T a2 = A.x * A.x + A.y * A.y + A.z * A.z;
+      const T ia = rsqrt_t(a2);
+      const T ar = a2 * ia;
+      T fca, dfca;
+      cut.eval(a2, fca, dfca);
+      const T pa = A.x * d0 + A.y * d1 + A.z * d2j;  // r_ij . (delta_j - delta_i)
+      for (int q = 0; q < nr; ++q) {
+        const T eta = tab->rad_eta[ec][f][q];
+        const T u = ar - tab->rad_rs[ec][f][q];
+        const T x = -eta * u * u;
+        const T ex = exp_scaled(x, x * T(1.4426950408889634));
+        const T dt = ex * (T(2) * ar * dfca - T(2) * eta * u * fca);  // dt/da
+        vs[tab->rad_out[ec][f][q]][lane] += (Acc)(dt * ia * pa);
+      }
+      const T inv_a2 = ia * ia;
+      for (int g = 0; g < n_el; ++g) {
+        AngClass<T> cl;
+        cl.load(tab, ec, class_index(min(f, g), max(f, g), n_el));
+        if (cl.na == 0) continue;
+        Acc vq[MAX_ANG];
+#pragma unroll
+        for (int q = 0; q < MAX_ANG; ++q) vq[q] = Acc(0);
+        for (int k = rw.lo(g); k < rw.lo(g + 1); ++k) {
+          const V4 B = row[k];
+          const T dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
+          const T d2 = dx * dx + dy * dy + dz * dz;
+          const bool near = d2 < rc2;
+          if (!(k != j && (near || cl.any_wide))) continue;
+          const T b2 = B.x * B.x + B.y * B.y + B.z * B.z;
+          const T ib = rsqrt_t(b2);
+          const T iab = ia * ib;
+          const T cs = (A.x * B.x + A.y * B.y + A.z * B.z) * iab;
+          const T fcb = cut.value(b2);
+          T fcd = T(0), dfcd = T(0);
+          if (near) cut.eval_in(d2, fcd, dfcd);
+          T ex[MAX_NE], exw[MAX_NE];
+#pragma unroll
+          for (int n = 0; n < MAX_NE; ++n) {
+            const T sn = a2 + b2 + d2, sw = a2 + b2;
+            ex[n] = n < ne && near && cl.any_narrow ? exp_scaled(-eta_n[n] * sn, -eta_n[n] * sn * T(1.4426950408889634)) : T(0);
+            exw[n] = n < ne && cl.any_wide ? exp_scaled(-eta_n[n] * sw, -eta_n[n] * sw * T(1.4426950408889634)) : T(0);
+          }
+          // projections of dcos/dr_j, r_ij and r_k - r_j on delta_j - delta_i
+          const T ca = cs * inv_a2;
+          const T pc = (B.x * d0 + B.y * d1 + B.z * d2j) * iab - ca * pa;
+          const T pd = dx * d0 + dy * d1 + dz * d2j;
+          const T f2 = fca * fcb;
+          const T f3 = f2 * fcd;
+#pragma unroll
+          for (int q = 0; q < MAX_ANG; ++q) {
+            if (q < cl.na) {
+              T pz, pz1;
+              powers(T(1) + cl.lam[q] * cs, cl.zl[q], pz, pz1);
+              T tc, ta, td;
+              if (cl.wide[q]) {
+                const T e = pick(exw, cl.ni[q]);
+                tc = e * cl.zeta[q] * cl.lam[q] * pz1 * f2;
+                ta = T(2) * e * pz * (dfca * fcb - cl.eta[q] * f2);
+                td = T(0);
+              } else {
+                const T e = pick(ex, cl.ni[q]);
+                tc = e * cl.zeta[q] * cl.lam[q] * pz1 * f3;
+                ta = T(2) * e * pz * (dfca * fcb * fcd - cl.eta[q] * f3);
+                td = T(2) * e * pz * (fca * fcb * dfcd - cl.eta[q] * f3);
+              }
+              vq[q] += (Acc)(tc * pc + ta * pa - td * pd);
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < MAX_ANG; ++q)
+          if (q < cl.na) vs[cl.out[q]][lane] += (Acc)cl.pre[q] * vq[q];
+      }
+    }
+  }
+  const int ns = tab->n_sf[ec];
+#pragma unroll
+  for (int s = 0; s < LD; ++s) a.V[c * LD + s] = s < ns ? (IO)vs[s][lane] : IO(0);
+}
+
 }  // namespace
 
 template <int P>
@@ -305,7 +422,8 @@ void launch_flat(int mode, const TripArgs<P>& a, hipStream_t stream) {
   if (a.n == 0) return;
   const unsigned nb = (unsigned)((a.n + FLAT - 1) / FLAT);
   if (mode == 0) hipLaunchKernelGGL(k_flat_sf<P>, dim3(nb), dim3(FLAT), 0, stream, a);
-  else hipLaunchKernelGGL(k_flat_force<P>, dim3(nb), dim3(FLAT), 0, stream, a);
+  else if (mode == 1) hipLaunchKernelGGL(k_flat_force<P>, dim3(nb), dim3(FLAT), 0, stream, a);
+  else hipLaunchKernelGGL(k_flat_jvp<P>, dim3(nb), dim3(FLAT), 0, stream, a);
 }
 
 template void launch_flat<P_FP64>(int, const TripArgs<P_FP64>&, hipStream_t);

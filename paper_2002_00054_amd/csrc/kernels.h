@@ -64,7 +64,7 @@ struct TripArgs {
 
 template <int P>
 void launch_triplet(int mode, int ne, const TripArgs<P>& a, hipStream_t stream);
-// One thread per centre (mode 0: SF, 1: force), for short neighbour rows.
+// One thread per centre (mode 0: SF, 1: force, 2: force-adjoint product).
 template <int P>
 void launch_flat(int mode, const TripArgs<P>& a, hipStream_t stream);
 template <int P>

@@ -2,8 +2,9 @@
 oracle at the usual bars: the fcc workload with its angular SFs made wide
 (up to the 1,492,992-atom box, sampled atoms there), and a two-element water
 table mixing narrow and wide functions in every neighbour class.  Tables
-with G9 run the thread-per-centre passes; the paths that do not support them
-report NNP_E_STATE."""
+with G9 run the thread-per-centre passes, the differentiation form included
+(its gradient against the oracle's); the stored-Jacobian variant reports
+NNP_E_STATE for them."""
 import numpy as np
 import pytest
 
@@ -88,18 +89,60 @@ def test_fcc_g9_fullsize_sampled():
     pot.close()
 
 
-def test_unsupported_paths_report_state_error():
-    import torch
-
+def test_stored_mode_reports_state_error():
     from paper_2002_00054_amd.nnp import NNPError
 
     table, nets, _ = _ni()
     pot = make_potential("fp64", table, nets)
     with pytest.raises(NNPError, match="NNP_E_STATE"):
         pot.set_derivative_mode("stored")
-    b = synth.fcc_box(3, 1)
-    pos = torch.tensor(b.pos, dtype=torch.float64, device="cuda")
-    types = torch.tensor(b.types, dtype=torch.int32, device="cuda")
-    with pytest.raises(NNPError, match="NNP_E_STATE"):
-        pot.backward(pos, types, [0, b.n_atoms], b.box[None])
+    pot.close()
+
+
+def _grad(pot, boxes, Ehat, Fhat, params):
+    import torch
+
+    from paper_2002_00054_amd.nnp import energy_forces
+
+    pos = torch.tensor(np.concatenate([b.pos for b in boxes]), dtype=torch.float64, device="cuda")
+    types = torch.tensor(np.concatenate([b.types for b in boxes]), dtype=torch.int32, device="cuda")
+    offs = np.cumsum([0] + [b.n_atoms for b in boxes])
+    th = torch.tensor(params, dtype=torch.float64, device="cuda", requires_grad=True)
+    E, F = energy_forces(th, pos, pot, types, offs, np.stack([b.box for b in boxes]))
+    N = torch.tensor([b.n_atoms for b in boxes], dtype=torch.float64, device="cuda")
+    L = torch.mean(((E - torch.tensor(Ehat, device="cuda")) / N) ** 2) + \
+        0.1 * torch.sum((F - torch.tensor(Fhat, device="cuda")) ** 2) / (3 * N.sum())
+    (g,) = torch.autograd.grad(L, th)
+    return L.item(), g.cpu().numpy()
+
+
+@pytest.mark.parametrize("which", ["fcc_g9", "water_mixed", "water_thread"])
+def test_weight_gradient_thread_per_centre(which):
+    """Differentiation form through the thread-per-centre passes (SF and
+    force-adjoint): G9 tables, and the narrow water table with the thread
+    level chosen explicitly, against the oracle's gradient (FP64)."""
+    if which == "fcc_g9":
+        table, nets, ref = _ni()
+        boxes = [synth.fcc_box(6, 5), synth.fcc_box(3, 6)]
+        n_el = 1
+    elif which == "water_mixed":
+        table, nets, ref = _water_mixed()
+        boxes = [synth.water_box(4, 41), synth.water_box(5, 42)]
+        n_el = 2
+    else:
+        table, nets = synth.water_table_scaled(), synth.water_nets()
+        ref = oracle.Potential(table, nets)
+        boxes = [synth.water_box(4, 41), synth.water_box(5, 42)]
+        n_el = 2
+    teacher = synth.xavier_nets(synth.sf_counts(table, n_el=n_el), 7, bias_halfwidth=0.1)
+    Ehat, Fhat = oracle.batch_energy_forces(oracle.Potential(table, teacher, n_el=n_el), boxes)
+    L_ref, g_ref = oracle.loss_and_grad(ref, boxes, Ehat, Fhat)
+    pot = make_potential("fp64", table, nets)
+    if which == "water_thread":
+        pot.set_parallelism("thread")
+    L, g = _grad(pot, boxes, Ehat, Fhat, synth.flat_params(nets))
+    rel = float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
+    say(which, "fp64 weight-gradient rel-L2", rel)
+    assert rel < 1e-8
+    assert L == pytest.approx(L_ref, rel=1e-10)
     pot.close()
