@@ -71,7 +71,7 @@ typedef enum { NNP_FP64 = 0, NNP_FP32 = 1, NNP_BF16_MIXED = 2 } nnp_precision;
  *            3 = narrow angular G3 (unordered neighbour-element pair nbr[0], nbr[1]);
  *            9 = wide angular G9 (same pair convention).  A table holding any
  *                G9 runs its SF, force and force-adjoint passes one thread per
- *                centre; NNP_DERIV_STORED then returns NNP_E_STATE.
+ *                centre (the stored-Jacobian variant handles G9 directly).
  *  eta       Gaussian exponent, A^-2, >= 0
  *  rs        radial shift, A (G2 only; must be 0 for G3 and G9)
  *  zeta      exponent, one of 1, 2, 4, 8, 16, 32 (G3 and G9 only)

@@ -1142,8 +1142,6 @@ nnp_status nnp_set_derivative_mode(nnp_handle* h, int mode) {
     return fail(h, NNP_E_ARG, "derivative mode must be NNP_DERIV_RECOMPUTE or NNP_DERIV_STORED");
   if (mode == NNP_DERIV_STORED && h->prec == NNP_BF16_MIXED)
     return fail(h, NNP_E_STATE, "the stored-Jacobian mode needs an NNP_FP64 or NNP_FP32 handle");
-  if (mode == NNP_DERIV_STORED && h->has_wide)
-    return fail(h, NNP_E_STATE, "the stored-Jacobian mode does not support wide angular SFs (kind 9)");
   if (mode != h->deriv_mode) h->jac_valid = false;
   h->deriv_mode = mode;
   return NNP_OK;

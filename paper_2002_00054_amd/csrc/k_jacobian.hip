@@ -146,10 +146,14 @@ __global__ void __launch_bounds__(256) k_jac(JacArgs<P> a) {
         const int ne = uniform(tab->n_eta[ec]);
         T qeta[MAX_ANG], qpre[MAX_ANG], qlam[MAX_ANG], qzeta[MAX_ANG];
         int qzl[MAX_ANG], qni[MAX_ANG];
+        bool qwide[MAX_ANG];  // wide function: no r_jk factor or cutoff
+        bool any_wide = false;
         T acc[MAX_ANG][3];
         T gacc[MAX_ANG];
 #pragma unroll
         for (int q = 0; q < MAX_ANG; ++q) {
+          qwide[q] = q < na && tab->ang_wide[ec][cls][q] != 0;
+          any_wide |= qwide[q];
           const int bit = q < na ? tab->ang_bit[ec][cls][q] : 0;
           const int qb = bit / MAX_NE;
           qni[q] = bit % MAX_NE;
@@ -169,36 +173,45 @@ __global__ void __launch_bounds__(256) k_jac(JacArgs<P> a) {
           const V4 xb = aux[k];
           const T dx = rb.x - ax, dy = rb.y - ay, dz = rb.z - az;
           const T d2 = dx * dx + dy * dy + dz * dz;
-          if (!(jv && k != t && d2 < rc2)) continue;
-          T fcd, dfcd;
-          cut.eval_in(d2, fcd, dfcd);
+          const bool near = d2 < rc2;
+          if (!(jv && k != t && (near || any_wide))) continue;
+          T fcd = T(0), dfcd = T(0);
+          if (near) cut.eval_in(d2, fcd, dfcd);
           const T b2 = rb.w, fcb = xb.y;
           const T inv_ab = T(1) / (ar * xb.x);
           const T cs = (ax * rb.x + ay * rb.y + az * rb.z) * inv_ab;
           const T ca = cs * inv_a2;
           const T gcx = rb.x * inv_ab - ca * ax, gcy = rb.y * inv_ab - ca * ay, gcz = rb.z * inv_ab - ca * az;
-          const T s2 = a2 + b2 + d2;
-          const T f3 = fca * fcb * fcd;
-          const T fa3 = dfca * fcb * fcd;
-          const T fd3 = fca * fcb * dfcd;
-          T exn[MAX_NE];
+          const T s2 = a2 + b2 + d2, sw = a2 + b2;
+          const T f2 = fca * fcb;
+          const T f3 = f2 * fcd;
+          T exn[MAX_NE], exw[MAX_NE];  // e^{-eta (a^2 + b^2 + d^2)} (narrow), e^{-eta (a^2 + b^2)} (wide)
 #pragma unroll
-          for (int n = 0; n < MAX_NE; ++n) exn[n] = n < ne ? exp_t(-eta_n[n] * s2) : T(0);
+          for (int n = 0; n < MAX_NE; ++n) {
+            exn[n] = n < ne && near ? exp_t(-eta_n[n] * s2) : T(0);
+            exw[n] = n < ne && any_wide ? exp_t(-eta_n[n] * sw) : T(0);
+          }
 #pragma unroll
           for (int q = 0; q < MAX_ANG; ++q) {
             if (q < na) {
               const int ni = qni[q];
-              const T ex = qpre[q] * (ni == 0 ? exn[0] : ni == 1 ? exn[1] : ni == 2 ? exn[2] : exn[3]);
+              const T en = ni == 0 ? exn[0] : ni == 1 ? exn[1] : ni == 2 ? exn[2] : exn[3];
+              const T ew = ni == 0 ? exw[0] : ni == 1 ? exw[1] : ni == 2 ? exw[2] : exw[3];
+              const T ex = qpre[q] * (qwide[q] ? ew : en);
               const T pb = T(1) + qlam[q] * cs;
               T pz1 = T(1), pw = pb;  // pb^(zeta - 1), pb^zeta
               for (int i = 0; i < qzl[q]; ++i) {
                 pz1 *= pw;
                 pw *= pw;
               }
-              const T tq = pw * ex * f3;
-              const T dtdc = qzeta[q] * qlam[q] * pz1 * ex * f3;
-              const T dta = T(2) * (-qeta[q] * tq + pw * ex * fa3);
-              const T dtd = T(2) * (-qeta[q] * tq + pw * ex * fd3);
+              // wide: the r_jk factor is 1 (no f_c(r_jk), no d^2 in the exponent)
+              const T fr = qwide[q] ? f2 : f3;
+              const T fa = qwide[q] ? dfca * fcb : dfca * fcb * fcd;
+              const T fd = qwide[q] ? T(0) : fca * fcb * dfcd;
+              const T tq = pw * ex * fr;
+              const T dtdc = qzeta[q] * qlam[q] * pz1 * ex * fr;
+              const T dta = T(2) * (-qeta[q] * tq + pw * ex * fa);
+              const T dtd = qwide[q] ? T(0) : T(2) * (-qeta[q] * tq + pw * ex * fd);
               acc[q][0] += dtdc * gcx + dta * ax - dtd * dx;
               acc[q][1] += dtdc * gcy + dta * ay - dtd * dy;
               acc[q][2] += dtdc * gcz + dta * az - dtd * dz;

@@ -3,8 +3,8 @@ oracle at the usual bars: the fcc workload with its angular SFs made wide
 (up to the 1,492,992-atom box, sampled atoms there), and a two-element water
 table mixing narrow and wide functions in every neighbour class.  Tables
 with G9 run the thread-per-centre passes, the differentiation form included
-(its gradient against the oracle's); the stored-Jacobian variant reports
-NNP_E_STATE for them."""
+(its gradient against the oracle's), and the stored-Jacobian variant handles
+them too."""
 import numpy as np
 import pytest
 
@@ -89,13 +89,15 @@ def test_fcc_g9_fullsize_sampled():
     pot.close()
 
 
-def test_stored_mode_reports_state_error():
-    from paper_2002_00054_amd.nnp import NNPError
-
-    table, nets, _ = _ni()
-    pot = make_potential("fp64", table, nets)
-    with pytest.raises(NNPError, match="NNP_E_STATE"):
-        pot.set_derivative_mode("stored")
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_stored_jacobian_forward_g9(form):
+    """The stored-Jacobian variant with wide functions: forces from the store."""
+    table, nets, ref_pot = _water_mixed()
+    b = synth.water_box(6, 7)
+    pot = make_potential(form, table, nets)
+    pot.set_derivative_mode("stored")
+    e, ei, f = run(pot, b)
+    _check(form, ei, f, ref_pot.compute(oracle_input(b, form), b.types, b.box, use_cells=True))
     pot.close()
 
 
@@ -116,16 +118,17 @@ def _grad(pot, boxes, Ehat, Fhat, params):
     return L.item(), g.cpu().numpy()
 
 
-@pytest.mark.parametrize("which", ["fcc_g9", "water_mixed", "water_thread"])
+@pytest.mark.parametrize("which", ["fcc_g9", "water_mixed", "water_thread", "water_mixed_stored"])
 def test_weight_gradient_thread_per_centre(which):
     """Differentiation form through the thread-per-centre passes (SF and
-    force-adjoint): G9 tables, and the narrow water table with the thread
-    level chosen explicitly, against the oracle's gradient (FP64)."""
+    force-adjoint): G9 tables, the narrow water table with the thread level
+    chosen explicitly, and a G9 table through the stored-Jacobian variant,
+    against the oracle's gradient (FP64)."""
     if which == "fcc_g9":
         table, nets, ref = _ni()
         boxes = [synth.fcc_box(6, 5), synth.fcc_box(3, 6)]
         n_el = 1
-    elif which == "water_mixed":
+    elif which.startswith("water_mixed"):
         table, nets, ref = _water_mixed()
         boxes = [synth.water_box(4, 41), synth.water_box(5, 42)]
         n_el = 2
@@ -140,6 +143,8 @@ def test_weight_gradient_thread_per_centre(which):
     pot = make_potential("fp64", table, nets)
     if which == "water_thread":
         pot.set_parallelism("thread")
+    if which == "water_mixed_stored":
+        pot.set_derivative_mode("stored")
     L, g = _grad(pot, boxes, Ehat, Fhat, synth.flat_params(nets))
     rel = float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
     say(which, "fp64 weight-gradient rel-L2", rel)
