@@ -129,6 +129,41 @@ def report(table, nets):
             del x, t
         pot.close()
         torch.cuda.empty_cache()
+    # differentiation form: one training step = forward of the batch + loss + weight gradient
+    boxes = synth.training_batch()
+    offs = np.cumsum([0] + [bx.n_atoms for bx in boxes])
+    bxs = np.stack([bx.box for bx in boxes])
+    rng = np.random.default_rng(5)
+    N = torch.tensor([bx.n_atoms for bx in boxes], dtype=torch.float64, device=dev)
+    Eh = torch.tensor(rng.normal(-1.5, 0.1, len(boxes)) * N.cpu().numpy(), dtype=torch.float64, device=dev)
+    Fhat = rng.normal(0.0, 1.0, (int(offs[-1]), 3))
+    for form, mode in (("fp32", "recompute"), ("fp32", "stored"), ("fp64", "recompute"), ("fp64", "stored")):
+        pot = Potential(table, nets, precision=form)
+        pot.set_derivative_mode(mode)
+        pos = torch.tensor(np.concatenate([bx.pos for bx in boxes]), dtype=pot.dtype, device=dev)
+        t = torch.tensor(np.concatenate([bx.types for bx in boxes]), dtype=torch.int32, device=dev)
+        Fh = torch.tensor(Fhat, dtype=pot.dtype, device=dev)
+        th = torch.tensor(synth.flat_params(nets), dtype=torch.float64, device=dev, requires_grad=True)
+
+        def step():
+            E, F = energy_forces(th, pos, pot, t, offs, bxs)
+            L = torch.mean(((E - Eh) / N) ** 2) + 0.1 * torch.sum((F - Fh).double() ** 2) / (3 * N.sum())
+            (g,) = torch.autograd.grad(L, th)
+            return g
+
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 5
+        print(json.dumps({"report": "training", "form": form, "derivatives": mode, "boxes": len(boxes),
+                          "atoms": int(offs[-1]), "ms_per_step": dt * 1e3,
+                          "workspace_gb": pot.workspace_bytes / 1e9}), flush=True)
+        pot.close()
+        torch.cuda.empty_cache()
     # second workload: single-element fcc metal, 3.9 A cutoff (the paper's Ni runs: ~1.5M atoms)
     from paper_2002_00054_amd import opcount
 
@@ -178,41 +213,6 @@ def report(table, nets):
             pot.close()
             del x, t
             torch.cuda.empty_cache()
-    # differentiation form: one training step = forward of the batch + loss + weight gradient
-    boxes = synth.training_batch()
-    offs = np.cumsum([0] + [bx.n_atoms for bx in boxes])
-    bxs = np.stack([bx.box for bx in boxes])
-    rng = np.random.default_rng(5)
-    N = torch.tensor([bx.n_atoms for bx in boxes], dtype=torch.float64, device=dev)
-    Eh = torch.tensor(rng.normal(-1.5, 0.1, len(boxes)) * N.cpu().numpy(), dtype=torch.float64, device=dev)
-    Fhat = rng.normal(0.0, 1.0, (int(offs[-1]), 3))
-    for form, mode in (("fp32", "recompute"), ("fp32", "stored"), ("fp64", "recompute"), ("fp64", "stored")):
-        pot = Potential(table, nets, precision=form)
-        pot.set_derivative_mode(mode)
-        pos = torch.tensor(np.concatenate([bx.pos for bx in boxes]), dtype=pot.dtype, device=dev)
-        t = torch.tensor(np.concatenate([bx.types for bx in boxes]), dtype=torch.int32, device=dev)
-        Fh = torch.tensor(Fhat, dtype=pot.dtype, device=dev)
-        th = torch.tensor(synth.flat_params(nets), dtype=torch.float64, device=dev, requires_grad=True)
-
-        def step():
-            E, F = energy_forces(th, pos, pot, t, offs, bxs)
-            L = torch.mean(((E - Eh) / N) ** 2) + 0.1 * torch.sum((F - Fh).double() ** 2) / (3 * N.sum())
-            (g,) = torch.autograd.grad(L, th)
-            return g
-
-        for _ in range(2):
-            step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(5):
-            step()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / 5
-        print(json.dumps({"report": "training", "form": form, "derivatives": mode, "boxes": len(boxes),
-                          "atoms": int(offs[-1]), "ms_per_step": dt * 1e3,
-                          "workspace_gb": pot.workspace_bytes / 1e9}), flush=True)
-        pot.close()
-        torch.cuda.empty_cache()
     # one energy+force evaluation with the stored-Jacobian forward (one eighth of the 2M box)
     bb = synth.water_box(44, 22)
     for mode in ("recompute", "stored"):

@@ -463,6 +463,7 @@ nnp_status jac_setup(nnp_handle* h, Common& cm, JacArgs<P>& j) {
   j.n = cm.B.n;
   j.cap = h->cap;
   j.lcap = h->lcap;
+  j.wide = h->has_wide ? 1 : 0;
   j.nbr = reinterpret_cast<const typename Vec4<T>::type*>(cm.nbr);
   j.nnb = cm.nnb;
   j.pos4 = cm.bin.pos4;

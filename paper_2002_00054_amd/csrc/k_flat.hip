@@ -17,6 +17,8 @@
 // polynomial, same angular factorisation):
 //   T = pre (1 + lam cos)^zeta e^{-eta (a^2 + b^2 + d^2)} fc(a) fc(b) fc(d),
 //   dT/dr_j = dT/dcos (r_ik/(a b) - cos r_ij/a^2) + 2 dT/d(a^2) r_ij - 2 dT/d(d^2) (r_k - r_j).
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace nnp {
@@ -138,32 +140,38 @@ __global__ void __launch_bounds__(FLAT) k_flat_sf(TripArgs<P> a) {
         const T a2 = A.x * A.x + A.y * A.y + A.z * A.z;
         const T ia = rsqrt_t(a2);
         const T fca = cut.value(a2);
-        for (int k = (f == g ? j + 1 : rw.lo(g)); k < rw.lo(g + 1); ++k) {
-          const V4 B = row[k];
-          const T dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
-          const T d2 = dx * dx + dy * dy + dz * dz;
-          const bool near = d2 < rc2;
-          if (!(near || cl.any_wide)) continue;
-          const T b2 = B.x * B.x + B.y * B.y + B.z * B.z;
-          const T cs = (A.x * B.x + A.y * B.y + A.z * B.z) * ia * rsqrt_t(b2);
-          const T f2 = fca * cut.value(b2);
-          const T f3 = near ? f2 * cut.value_in(d2) : T(0);
-          T ex[MAX_NE], exw[MAX_NE];  // e^{-eta (a^2 + b^2 + d^2)} (narrow), e^{-eta (a^2 + b^2)} (wide)
-#pragma unroll
-          for (int n = 0; n < MAX_NE; ++n) {
-            const T sn = a2 + b2 + d2, sw = a2 + b2;
-            ex[n] = n < ne && near && cl.any_narrow ? exp_scaled(-eta_n[n] * sn, -eta_n[n] * sn * T(1.4426950408889634)) : T(0);
-            exw[n] = n < ne && cl.any_wide ? exp_scaled(-eta_n[n] * sw, -eta_n[n] * sw * T(1.4426950408889634)) : T(0);
-          }
-#pragma unroll
-          for (int q = 0; q < MAX_ANG; ++q) {
-            if (q < cl.na) {
-              T pz, pz1;
-              powers(T(1) + cl.lam[q] * cs, cl.zl[q], pz, pz1);
-              gq[q] += (Acc)(cl.wide[q] ? pz * pick(exw, cl.ni[q]) * f2 : pz * pick(ex, cl.ni[q]) * f3);
+        // the pair loop, compiled without the wide terms where a class has none
+        auto pairs = [&](auto wide_tag) {
+          constexpr bool W = decltype(wide_tag)::value;
+          for (int k = (f == g ? j + 1 : rw.lo(g)); k < rw.lo(g + 1); ++k) {
+            const V4 B = row[k];
+            const T dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
+            const T d2 = dx * dx + dy * dy + dz * dz;
+            const bool near = d2 < rc2;
+            if (!(near || W)) continue;
+            const T b2 = B.x * B.x + B.y * B.y + B.z * B.z;
+            const T cs = (A.x * B.x + A.y * B.y + A.z * B.z) * ia * rsqrt_t(b2);
+            const T f2 = fca * cut.value(b2);
+            const T f3 = near ? f2 * cut.value_in(d2) : T(0);
+            T ex[MAX_NE], exw[MAX_NE];  // e^{-eta (a^2 + b^2 + d^2)} (narrow), e^{-eta (a^2 + b^2)} (wide)
+  #pragma unroll
+            for (int n = 0; n < MAX_NE; ++n) {
+              const T sn = a2 + b2 + d2, sw = a2 + b2;
+              ex[n] = n < ne && near && cl.any_narrow ? exp_scaled(-eta_n[n] * sn, -eta_n[n] * sn * T(1.4426950408889634)) : T(0);
+              exw[n] = W && n < ne ? exp_scaled(-eta_n[n] * sw, -eta_n[n] * sw * T(1.4426950408889634)) : T(0);
+            }
+  #pragma unroll
+            for (int q = 0; q < MAX_ANG; ++q) {
+              if (q < cl.na) {
+                T pz, pz1;
+                powers(T(1) + cl.lam[q] * cs, cl.zl[q], pz, pz1);
+                gq[q] += (Acc)((W && cl.wide[q]) ? pz * pick(exw, cl.ni[q]) * f2 : pz * pick(ex, cl.ni[q]) * f3);
+              }
             }
           }
-        }
+        };
+        if (cl.any_wide) pairs(std::true_type{});
+        else pairs(std::false_type{});
       }
 #pragma unroll
       for (int q = 0; q < MAX_ANG; ++q)
@@ -233,56 +241,62 @@ __global__ void __launch_bounds__(FLAT) k_flat_force(TripArgs<P> a) {
         T w[MAX_ANG];
 #pragma unroll
         for (int q = 0; q < MAX_ANG; ++q) w[q] = q < cl.na ? cf[cl.out[q]][lane] * cl.pre[q] : T(0);
-        for (int k = rw.lo(g); k < rw.lo(g + 1); ++k) {
-          const V4 B = row[k];
-          const T dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
-          const T d2 = dx * dx + dy * dy + dz * dz;
-          const bool near = d2 < rc2;
-          if (!(k != j && (near || cl.any_wide))) continue;
-          const T b2 = B.x * B.x + B.y * B.y + B.z * B.z;
-          const T ib = rsqrt_t(b2);
-          const T iab = ia * ib;
-          const T cs = (A.x * B.x + A.y * B.y + A.z * B.z) * iab;
-          const T fcb = cut.value(b2);
-          T fcd = T(0), dfcd = T(0);
-          if (near) cut.eval_in(d2, fcd, dfcd);
-          T ex[MAX_NE], exw[MAX_NE];  // e^{-eta (a^2 + b^2 + d^2)} (narrow), e^{-eta (a^2 + b^2)} (wide)
-#pragma unroll
-          for (int n = 0; n < MAX_NE; ++n) {
-            const T sn = a2 + b2 + d2, sw = a2 + b2;
-            ex[n] = n < ne && near && cl.any_narrow ? exp_scaled(-eta_n[n] * sn, -eta_n[n] * sn * T(1.4426950408889634)) : T(0);
-            exw[n] = n < ne && cl.any_wide ? exp_scaled(-eta_n[n] * sw, -eta_n[n] * sw * T(1.4426950408889634)) : T(0);
-          }
-          // narrow (n) and wide (w) sums: Uc = sum_q w zeta lam pz1 E, Uz = sum_q w pz E, Ue = sum_q w eta pz E
-          T Ucn = T(0), Uzn = T(0), Uen = T(0), Ucw = T(0), Uzw = T(0), Uew = T(0);
-#pragma unroll
-          for (int q = 0; q < MAX_ANG; ++q) {
-            if (q < cl.na) {
-              T pz, pz1;
-              powers(T(1) + cl.lam[q] * cs, cl.zl[q], pz, pz1);
-              const T we = w[q] * (cl.wide[q] ? pick(exw, cl.ni[q]) : pick(ex, cl.ni[q]));
-              const T c1 = we * cl.zeta[q] * cl.lam[q] * pz1, c2 = we * pz, c3 = we * cl.eta[q] * pz;
-              if (cl.wide[q]) {
-                Ucw += c1;
-                Uzw += c2;
-                Uew += c3;
-              } else {
-                Ucn += c1;
-                Uzn += c2;
-                Uen += c3;
+        // the pair loop, compiled without the wide terms where a class has none
+        auto pairs = [&](auto wide_tag) {
+          constexpr bool W = decltype(wide_tag)::value;
+          for (int k = rw.lo(g); k < rw.lo(g + 1); ++k) {
+            const V4 B = row[k];
+            const T dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
+            const T d2 = dx * dx + dy * dy + dz * dz;
+            const bool near = d2 < rc2;
+            if (!(k != j && (near || W))) continue;
+            const T b2 = B.x * B.x + B.y * B.y + B.z * B.z;
+            const T ib = rsqrt_t(b2);
+            const T iab = ia * ib;
+            const T cs = (A.x * B.x + A.y * B.y + A.z * B.z) * iab;
+            const T fcb = cut.value(b2);
+            T fcd = T(0), dfcd = T(0);
+            if (near) cut.eval_in(d2, fcd, dfcd);
+            T ex[MAX_NE], exw[MAX_NE];  // e^{-eta (a^2 + b^2 + d^2)} (narrow), e^{-eta (a^2 + b^2)} (wide)
+  #pragma unroll
+            for (int n = 0; n < MAX_NE; ++n) {
+              const T sn = a2 + b2 + d2, sw = a2 + b2;
+              ex[n] = n < ne && near && cl.any_narrow ? exp_scaled(-eta_n[n] * sn, -eta_n[n] * sn * T(1.4426950408889634)) : T(0);
+              exw[n] = W && n < ne ? exp_scaled(-eta_n[n] * sw, -eta_n[n] * sw * T(1.4426950408889634)) : T(0);
+            }
+            // narrow (n) and wide (w) sums: Uc = sum_q w zeta lam pz1 E, Uz = sum_q w pz E, Ue = sum_q w eta pz E
+            T Ucn = T(0), Uzn = T(0), Uen = T(0), Ucw = T(0), Uzw = T(0), Uew = T(0);
+  #pragma unroll
+            for (int q = 0; q < MAX_ANG; ++q) {
+              if (q < cl.na) {
+                T pz, pz1;
+                powers(T(1) + cl.lam[q] * cs, cl.zl[q], pz, pz1);
+                const T we = w[q] * ((W && cl.wide[q]) ? pick(exw, cl.ni[q]) : pick(ex, cl.ni[q]));
+                const T c1 = we * cl.zeta[q] * cl.lam[q] * pz1, c2 = we * pz, c3 = we * cl.eta[q] * pz;
+                if ((W && cl.wide[q])) {
+                  Ucw += c1;
+                  Uzw += c2;
+                  Uew += c3;
+                } else {
+                  Ucn += c1;
+                  Uzn += c2;
+                  Uen += c3;
+                }
               }
             }
+            const T f2 = fca * fcb;
+            const T f3 = f2 * fcd;
+            const T tc = Ucn * f3 + Ucw * f2;                                                     // dT/dcos
+            const T ta = T(2) * (Uzn * dfca * fcb * fcd - Uen * f3 + Uzw * dfca * fcb - Uew * f2);  // 2 dT/d(a^2)
+            const T td = T(2) * (Uzn * fca * fcb * dfcd - Uen * f3);                               // 2 dT/d(d^2)
+            const T ca = cs * inv_a2;
+            gx += tc * (B.x * iab - ca * A.x) + ta * A.x - td * dx;
+            gy += tc * (B.y * iab - ca * A.y) + ta * A.y - td * dy;
+            gz += tc * (B.z * iab - ca * A.z) + ta * A.z - td * dz;
           }
-          const T f2 = fca * fcb;
-          const T f3 = f2 * fcd;
-          const T tc = Ucn * f3 + Ucw * f2;                                                     // dT/dcos
-          const T ta = T(2) * (Uzn * dfca * fcb * fcd - Uen * f3 + Uzw * dfca * fcb - Uew * f2);  // 2 dT/d(a^2)
-          const T td = T(2) * (Uzn * fca * fcb * dfcd - Uen * f3);                               // 2 dT/d(d^2)
-          const T ca = cs * inv_a2;
-          gx += tc * (B.x * iab - ca * A.x) + ta * A.x - td * dx;
-          gy += tc * (B.y * iab - ca * A.y) + ta * A.y - td * dy;
-          gz += tc * (B.z * iab - ca * A.z) + ta * A.z - td * dz;
-        }
+        };
+        if (cl.any_wide) pairs(std::true_type{});
+        else pairs(std::false_type{});
       }
       const int64_t jj = entry_index(A);
       atomic_add(&a.F[3 * jj + 0], (FAcc)(-gx));
@@ -357,53 +371,59 @@ __global__ void __launch_bounds__(FLAT) k_flat_jvp(TripArgs<P> a) {
         Acc vq[MAX_ANG];
 #pragma unroll
         for (int q = 0; q < MAX_ANG; ++q) vq[q] = Acc(0);
-        for (int k = rw.lo(g); k < rw.lo(g + 1); ++k) {
-          const V4 B = row[k];
-          const T dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
-          const T d2 = dx * dx + dy * dy + dz * dz;
-          const bool near = d2 < rc2;
-          if (!(k != j && (near || cl.any_wide))) continue;
-          const T b2 = B.x * B.x + B.y * B.y + B.z * B.z;
-          const T ib = rsqrt_t(b2);
-          const T iab = ia * ib;
-          const T cs = (A.x * B.x + A.y * B.y + A.z * B.z) * iab;
-          const T fcb = cut.value(b2);
-          T fcd = T(0), dfcd = T(0);
-          if (near) cut.eval_in(d2, fcd, dfcd);
-          T ex[MAX_NE], exw[MAX_NE];
-#pragma unroll
-          for (int n = 0; n < MAX_NE; ++n) {
-            const T sn = a2 + b2 + d2, sw = a2 + b2;
-            ex[n] = n < ne && near && cl.any_narrow ? exp_scaled(-eta_n[n] * sn, -eta_n[n] * sn * T(1.4426950408889634)) : T(0);
-            exw[n] = n < ne && cl.any_wide ? exp_scaled(-eta_n[n] * sw, -eta_n[n] * sw * T(1.4426950408889634)) : T(0);
-          }
-          // projections of dcos/dr_j, r_ij and r_k - r_j on delta_j - delta_i
-          const T ca = cs * inv_a2;
-          const T pc = (B.x * d0 + B.y * d1 + B.z * d2j) * iab - ca * pa;
-          const T pd = dx * d0 + dy * d1 + dz * d2j;
-          const T f2 = fca * fcb;
-          const T f3 = f2 * fcd;
-#pragma unroll
-          for (int q = 0; q < MAX_ANG; ++q) {
-            if (q < cl.na) {
-              T pz, pz1;
-              powers(T(1) + cl.lam[q] * cs, cl.zl[q], pz, pz1);
-              T tc, ta, td;
-              if (cl.wide[q]) {
-                const T e = pick(exw, cl.ni[q]);
-                tc = e * cl.zeta[q] * cl.lam[q] * pz1 * f2;
-                ta = T(2) * e * pz * (dfca * fcb - cl.eta[q] * f2);
-                td = T(0);
-              } else {
-                const T e = pick(ex, cl.ni[q]);
-                tc = e * cl.zeta[q] * cl.lam[q] * pz1 * f3;
-                ta = T(2) * e * pz * (dfca * fcb * fcd - cl.eta[q] * f3);
-                td = T(2) * e * pz * (fca * fcb * dfcd - cl.eta[q] * f3);
+        // the pair loop, compiled without the wide terms where a class has none
+        auto pairs = [&](auto wide_tag) {
+          constexpr bool W = decltype(wide_tag)::value;
+          for (int k = rw.lo(g); k < rw.lo(g + 1); ++k) {
+            const V4 B = row[k];
+            const T dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
+            const T d2 = dx * dx + dy * dy + dz * dz;
+            const bool near = d2 < rc2;
+            if (!(k != j && (near || W))) continue;
+            const T b2 = B.x * B.x + B.y * B.y + B.z * B.z;
+            const T ib = rsqrt_t(b2);
+            const T iab = ia * ib;
+            const T cs = (A.x * B.x + A.y * B.y + A.z * B.z) * iab;
+            const T fcb = cut.value(b2);
+            T fcd = T(0), dfcd = T(0);
+            if (near) cut.eval_in(d2, fcd, dfcd);
+            T ex[MAX_NE], exw[MAX_NE];
+  #pragma unroll
+            for (int n = 0; n < MAX_NE; ++n) {
+              const T sn = a2 + b2 + d2, sw = a2 + b2;
+              ex[n] = n < ne && near && cl.any_narrow ? exp_scaled(-eta_n[n] * sn, -eta_n[n] * sn * T(1.4426950408889634)) : T(0);
+              exw[n] = W && n < ne ? exp_scaled(-eta_n[n] * sw, -eta_n[n] * sw * T(1.4426950408889634)) : T(0);
+            }
+            // projections of dcos/dr_j, r_ij and r_k - r_j on delta_j - delta_i
+            const T ca = cs * inv_a2;
+            const T pc = (B.x * d0 + B.y * d1 + B.z * d2j) * iab - ca * pa;
+            const T pd = dx * d0 + dy * d1 + dz * d2j;
+            const T f2 = fca * fcb;
+            const T f3 = f2 * fcd;
+  #pragma unroll
+            for (int q = 0; q < MAX_ANG; ++q) {
+              if (q < cl.na) {
+                T pz, pz1;
+                powers(T(1) + cl.lam[q] * cs, cl.zl[q], pz, pz1);
+                T tc, ta, td;
+                if ((W && cl.wide[q])) {
+                  const T e = pick(exw, cl.ni[q]);
+                  tc = e * cl.zeta[q] * cl.lam[q] * pz1 * f2;
+                  ta = T(2) * e * pz * (dfca * fcb - cl.eta[q] * f2);
+                  td = T(0);
+                } else {
+                  const T e = pick(ex, cl.ni[q]);
+                  tc = e * cl.zeta[q] * cl.lam[q] * pz1 * f3;
+                  ta = T(2) * e * pz * (dfca * fcb * fcd - cl.eta[q] * f3);
+                  td = T(2) * e * pz * (fca * fcb * dfcd - cl.eta[q] * f3);
+                }
+                vq[q] += (Acc)(tc * pc + ta * pa - td * pd);
               }
-              vq[q] += (Acc)(tc * pc + ta * pa - td * pd);
             }
           }
-        }
+        };
+        if (cl.any_wide) pairs(std::true_type{});
+        else pairs(std::false_type{});
 #pragma unroll
         for (int q = 0; q < MAX_ANG; ++q)
           if (q < cl.na) vs[cl.out[q]][lane] += (Acc)cl.pre[q] * vq[q];

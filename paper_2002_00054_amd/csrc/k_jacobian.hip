@@ -22,6 +22,8 @@
 // neighbour k of the centre, so each lane accumulates only its own row of J in
 // registers: no atomics and no LDS slot sums, at the price of visiting every
 // triplet twice (once from j, once from k).
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace nnp {
@@ -39,7 +41,9 @@ constexpr size_t jac_wave_bytes_of(int lcap) {
 __device__ inline float exp_t(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
 __device__ inline double exp_t(double x) { return exp(x); }
 
-template <int P>
+// WIDE: the table holds wide angular functions (a separate instantiation, so
+// that narrow-only tables keep the register count of the narrow loop).
+template <int P, bool WIDE>
 __global__ void __launch_bounds__(256) k_jac(JacArgs<P> a) {
   using T = typename Types<P>::T;
   using Acc = typename Types<P>::Acc;
@@ -168,56 +172,112 @@ __global__ void __launch_bounds__(256) k_jac(JacArgs<P> a) {
         T eta_n[MAX_NE];
 #pragma unroll
         for (int n = 0; n < MAX_NE; ++n) eta_n[n] = n < ne ? tab->aeta[ec][n] : T(0);
-        for (int k = off[g]; k < off[g + 1]; ++k) {
-          const V4 rb = rec[k];
-          const V4 xb = aux[k];
-          const T dx = rb.x - ax, dy = rb.y - ay, dz = rb.z - az;
-          const T d2 = dx * dx + dy * dy + dz * dz;
-          const bool near = d2 < rc2;
-          if (!(jv && k != t && (near || any_wide))) continue;
-          T fcd = T(0), dfcd = T(0);
-          if (near) cut.eval_in(d2, fcd, dfcd);
-          const T b2 = rb.w, fcb = xb.y;
-          const T inv_ab = T(1) / (ar * xb.x);
-          const T cs = (ax * rb.x + ay * rb.y + az * rb.z) * inv_ab;
-          const T ca = cs * inv_a2;
-          const T gcx = rb.x * inv_ab - ca * ax, gcy = rb.y * inv_ab - ca * ay, gcz = rb.z * inv_ab - ca * az;
-          const T s2 = a2 + b2 + d2, sw = a2 + b2;
-          const T f2 = fca * fcb;
-          const T f3 = f2 * fcd;
-          T exn[MAX_NE], exw[MAX_NE];  // e^{-eta (a^2 + b^2 + d^2)} (narrow), e^{-eta (a^2 + b^2)} (wide)
-#pragma unroll
-          for (int n = 0; n < MAX_NE; ++n) {
-            exn[n] = n < ne && near ? exp_t(-eta_n[n] * s2) : T(0);
-            exw[n] = n < ne && any_wide ? exp_t(-eta_n[n] * sw) : T(0);
-          }
-#pragma unroll
-          for (int q = 0; q < MAX_ANG; ++q) {
-            if (q < na) {
-              const int ni = qni[q];
-              const T en = ni == 0 ? exn[0] : ni == 1 ? exn[1] : ni == 2 ? exn[2] : exn[3];
-              const T ew = ni == 0 ? exw[0] : ni == 1 ? exw[1] : ni == 2 ? exw[2] : exw[3];
-              const T ex = qpre[q] * (qwide[q] ? ew : en);
-              const T pb = T(1) + qlam[q] * cs;
-              T pz1 = T(1), pw = pb;  // pb^(zeta - 1), pb^zeta
-              for (int i = 0; i < qzl[q]; ++i) {
-                pz1 *= pw;
-                pw *= pw;
+        // the pair loop, compiled without the wide terms for classes that have none
+        auto pairs = [&](auto wide_tag) {
+          constexpr bool W = decltype(wide_tag)::value;
+          if constexpr (W) {
+            for (int k = off[g]; k < off[g + 1]; ++k) {
+              const V4 rb = rec[k];
+              const V4 xb = aux[k];
+              const T dx = rb.x - ax, dy = rb.y - ay, dz = rb.z - az;
+              const T d2 = dx * dx + dy * dy + dz * dz;
+              const bool near = d2 < rc2;
+              if (!(jv && k != t && (near || W))) continue;
+              T fcd = T(0), dfcd = T(0);
+              if (near) cut.eval_in(d2, fcd, dfcd);
+              const T b2 = rb.w, fcb = xb.y;
+              const T inv_ab = T(1) / (ar * xb.x);
+              const T cs = (ax * rb.x + ay * rb.y + az * rb.z) * inv_ab;
+              const T ca = cs * inv_a2;
+              const T gcx = rb.x * inv_ab - ca * ax, gcy = rb.y * inv_ab - ca * ay, gcz = rb.z * inv_ab - ca * az;
+              const T s2 = a2 + b2 + d2, sw = a2 + b2;
+              const T f2 = fca * fcb;
+              const T f3 = f2 * fcd;
+              T exn[MAX_NE], exw[MAX_NE];  // e^{-eta (a^2 + b^2 + d^2)} (narrow), e^{-eta (a^2 + b^2)} (wide)
+    #pragma unroll
+              for (int n = 0; n < MAX_NE; ++n) {
+                exn[n] = n < ne && near ? exp_t(-eta_n[n] * s2) : T(0);
+                exw[n] = W && n < ne ? exp_t(-eta_n[n] * sw) : T(0);
               }
-              // wide: the r_jk factor is 1 (no f_c(r_jk), no d^2 in the exponent)
-              const T fr = qwide[q] ? f2 : f3;
-              const T fa = qwide[q] ? dfca * fcb : dfca * fcb * fcd;
-              const T fd = qwide[q] ? T(0) : fca * fcb * dfcd;
-              const T tq = pw * ex * fr;
-              const T dtdc = qzeta[q] * qlam[q] * pz1 * ex * fr;
-              const T dta = T(2) * (-qeta[q] * tq + pw * ex * fa);
-              const T dtd = qwide[q] ? T(0) : T(2) * (-qeta[q] * tq + pw * ex * fd);
-              acc[q][0] += dtdc * gcx + dta * ax - dtd * dx;
-              acc[q][1] += dtdc * gcy + dta * ay - dtd * dy;
-              acc[q][2] += dtdc * gcz + dta * az - dtd * dz;
-              gacc[q] += tq;
+    #pragma unroll
+              for (int q = 0; q < MAX_ANG; ++q) {
+                if (q < na) {
+                  const int ni = qni[q];
+                  const T en = ni == 0 ? exn[0] : ni == 1 ? exn[1] : ni == 2 ? exn[2] : exn[3];
+                  const T ew = ni == 0 ? exw[0] : ni == 1 ? exw[1] : ni == 2 ? exw[2] : exw[3];
+                  const bool wq = W && qwide[q];
+                  const T ex = qpre[q] * (wq ? ew : en);
+                  const T pb = T(1) + qlam[q] * cs;
+                  T pz1 = T(1), pw = pb;  // pb^(zeta - 1), pb^zeta
+                  for (int i = 0; i < qzl[q]; ++i) {
+                    pz1 *= pw;
+                    pw *= pw;
+                  }
+                  // wide: the r_jk factor is 1 (no f_c(r_jk), no d^2 in the exponent)
+                  const T fr = wq ? f2 : f3;
+                  const T fa = wq ? dfca * fcb : dfca * fcb * fcd;
+                  const T fd = wq ? T(0) : fca * fcb * dfcd;
+                  const T tq = pw * ex * fr;
+                  const T dtdc = qzeta[q] * qlam[q] * pz1 * ex * fr;
+                  const T dta = T(2) * (-qeta[q] * tq + pw * ex * fa);
+                  const T dtd = wq ? T(0) : T(2) * (-qeta[q] * tq + pw * ex * fd);
+                  acc[q][0] += dtdc * gcx + dta * ax - dtd * dx;
+                  acc[q][1] += dtdc * gcy + dta * ay - dtd * dy;
+                  acc[q][2] += dtdc * gcz + dta * az - dtd * dz;
+                  gacc[q] += tq;
+                }
+              }
+            }
+          } else {  // narrow functions only
+            for (int k = off[g]; k < off[g + 1]; ++k) {
+              const V4 rb = rec[k];
+              const V4 xb = aux[k];
+              const T dx = rb.x - ax, dy = rb.y - ay, dz = rb.z - az;
+              const T d2 = dx * dx + dy * dy + dz * dz;
+              if (!(jv && k != t && d2 < rc2)) continue;
+              T fcd, dfcd;
+              cut.eval_in(d2, fcd, dfcd);
+              const T b2 = rb.w, fcb = xb.y;
+              const T inv_ab = T(1) / (ar * xb.x);
+              const T cs = (ax * rb.x + ay * rb.y + az * rb.z) * inv_ab;
+              const T ca = cs * inv_a2;
+              const T gcx = rb.x * inv_ab - ca * ax, gcy = rb.y * inv_ab - ca * ay, gcz = rb.z * inv_ab - ca * az;
+              const T s2 = a2 + b2 + d2;
+              const T f3 = fca * fcb * fcd;
+              const T fa3 = dfca * fcb * fcd;
+              const T fd3 = fca * fcb * dfcd;
+              T exn[MAX_NE];
+    #pragma unroll
+              for (int n = 0; n < MAX_NE; ++n) exn[n] = n < ne ? exp_t(-eta_n[n] * s2) : T(0);
+    #pragma unroll
+              for (int q = 0; q < MAX_ANG; ++q) {
+                if (q < na) {
+                  const int ni = qni[q];
+                  const T ex = qpre[q] * (ni == 0 ? exn[0] : ni == 1 ? exn[1] : ni == 2 ? exn[2] : exn[3]);
+                  const T pb = T(1) + qlam[q] * cs;
+                  T pz1 = T(1), pw = pb;  // pb^(zeta - 1), pb^zeta
+                  for (int i = 0; i < qzl[q]; ++i) {
+                    pz1 *= pw;
+                    pw *= pw;
+                  }
+                  const T tq = pw * ex * f3;
+                  const T dtdc = qzeta[q] * qlam[q] * pz1 * ex * f3;
+                  const T dta = T(2) * (-qeta[q] * tq + pw * ex * fa3);
+                  const T dtd = T(2) * (-qeta[q] * tq + pw * ex * fd3);
+                  acc[q][0] += dtdc * gcx + dta * ax - dtd * dx;
+                  acc[q][1] += dtdc * gcy + dta * ay - dtd * dy;
+                  acc[q][2] += dtdc * gcz + dta * az - dtd * dz;
+                  gacc[q] += tq;
+                }
+              }
             }
           }
+        };
+        if constexpr (WIDE) {
+          if (any_wide) pairs(std::true_type{});
+          else pairs(std::false_type{});
+        } else {
+          pairs(std::false_type{});
         }
 #pragma unroll
         for (int q = 0; q < MAX_ANG; ++q) {
@@ -362,10 +422,13 @@ template <int P>
 void launch_jac(const JacArgs<P>& a, hipStream_t stream) {
   if (a.n == 0) return;
   const size_t lds = jac_lds_bytes<P>(a.lcap);
-  if (lds > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_jac<P>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-  hipLaunchKernelGGL(k_jac<P>, dim3((unsigned)wave_blocks(a.n)), dim3(256), lds, stream, a);
+  const void* fn = a.wide ? reinterpret_cast<const void*>(&k_jac<P, true>)
+                          : reinterpret_cast<const void*>(&k_jac<P, false>);
+  if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (a.wide)
+    hipLaunchKernelGGL((k_jac<P, true>), dim3((unsigned)wave_blocks(a.n)), dim3(256), lds, stream, a);
+  else
+    hipLaunchKernelGGL((k_jac<P, false>), dim3((unsigned)wave_blocks(a.n)), dim3(256), lds, stream, a);
 }
 
 template <int P>

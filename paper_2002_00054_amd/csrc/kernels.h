@@ -82,6 +82,7 @@ struct JacArgs {
   int64_t n;                 // sorted atoms
   int cap;                   // neighbour slots per atom
   int lcap;                  // >= the most neighbours of any atom
+  int wide;                  // the table holds wide angular functions
   const typename Vec4<T>::type* nbr;  // [n][cap] (dx, dy, dz, j) entries
   const int4* nnb;           // [n] neighbours per element block
   const double4* pos4;       // sorted positions + ids
