@@ -73,6 +73,8 @@ def _create(table, nets, precision="fp64"):
     (lambda t: setattr(t[3], "centre", 5), "centre"),
     (lambda t: setattr(t[3], "eta", -1.0), "eta"),
     (lambda t: setattr(t[45], "rs", 1.0), "rs"),
+    (lambda t: setattr(t[45], "kind", 5), "kind"),
+    (lambda t: (setattr(t[45], "kind", 9), setattr(t[45], "zeta", 3.0)), "zeta"),
 ])
 def test_bad_table_rejected(mutate, match):
     from paper_2002_00054_amd.nnp import NNPError
