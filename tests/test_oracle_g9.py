@@ -104,3 +104,15 @@ def test_rotation_invariance():
     R = random_rotation(rng)
     e1 = pot.compute(pts @ R.T + 20.0, types, box)["Ei"]
     np.testing.assert_allclose(e1, e0, rtol=1e-12, atol=1e-12)
+
+
+def test_sampled_matches_full_with_wide_functions():
+    """The sampled evaluator (used at full size) equals the full one on a mixed table."""
+    table = [synth.SF(0, 2, (0,), eta, rc=RC) for eta in synth.NI_RADIAL_ETAS[:4]] + _table(3) + _table(9)
+    pot = _pot(table)
+    b = synth.fcc_box(4, 8)
+    full = pot.compute(b.pos, b.types, b.box, use_cells=True)
+    idx = np.array([0, 5, 77, 130, 255], dtype=np.int64)
+    Ei, F = pot.sampled(b.pos, b.types, b.box, idx)
+    np.testing.assert_allclose(Ei, full["Ei"][idx], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(F, full["F"][idx], rtol=1e-11, atol=1e-12)
