@@ -8,7 +8,8 @@
 - the perfect fcc lattice: every G9 equals the sum over all 153 unordered
   pairs of the 18 neighbour vectors, from exact integer vectors;
 - forces of a mixed narrow + wide table against central differences of E;
-- rotation invariance of a cluster.
+- rotation invariance of a cluster;
+- the sampled evaluator (used at full size) against the full one.
 """
 import itertools
 import math
