@@ -70,3 +70,39 @@ def test_bad_mode():
     with pytest.raises(NNPError, match="NNP_E_ARG"):
         pot._check(pot._L.nnp_set_parallelism(pot._h, 9))
     pot.close()
+
+
+def _dense_ball():
+    """A jittered cubic lattice (spacing 0.56 A) inside a ball of radius 2.9 A,
+    H and O mixed: ~580 atoms, every pair closer than rc = 6 A."""
+    rng = np.random.default_rng(17)
+    g = np.arange(-2.9, 2.9001, 0.56)
+    pts = np.array([(x, y, z) for x in g for y in g for z in g])
+    pts = pts[np.einsum("ij,ij->i", pts, pts) <= 2.9 ** 2]
+    pts = pts + rng.uniform(-0.04, 0.04, pts.shape)
+    types = np.where(np.arange(len(pts)) % 3 == 0, synth.O, synth.H).astype(np.int32)
+    return synth.Box(pos=pts + 7.0, types=types, box=np.array([14.0, 14.0, 14.0]))
+
+
+def test_dense_cluster_beyond_wave_lds():
+    """Atoms with more neighbours than the wave level can stage in LDS (about
+    580 per atom: over 190 KB per workgroup in FP64, above the 160 KB a
+    workgroup can have) are refused by the wave level with NNP_E_ARG before
+    any launch; on the same handle the thread level, which reads the rows
+    from HBM, computes them, against the oracle (FP64)."""
+    from paper_2002_00054_amd.nnp import NNPError
+
+    b = _dense_ball()
+    assert b.n_atoms > 560
+    d2 = np.sum((b.pos[:, None, :] - b.pos[None, :, :]) ** 2, axis=-1)
+    assert np.max(d2) < synth.RCUT ** 2
+    say("dense ball", b.n_atoms)
+    pot = make_potential("fp64")
+    with pytest.raises(NNPError, match="NNP_E_ARG.*LDS"):
+        run(pot, b)
+    pot.set_parallelism("thread")
+    e, ei, f = run(pot, b)
+    ref = oracle_water().compute(b.pos, b.types, b.box, use_cells=True)
+    check_fp64(ei, f, ref["Ei"], ref["F"])
+    assert e == pytest.approx(float(np.sum(ref["Ei"])), rel=1e-10)
+    pot.close()
