@@ -26,8 +26,14 @@
  * box edge > 2 rc.  Positions may lie outside the box; they are wrapped.
  *
  * Threading: a handle may be used by one host thread and one stream at a time.
- * All work of a call is enqueued on the caller's stream; calls that return a
- * host value (the energy) or detect errors synchronise that stream.
+ * A call that overlaps another call on the same handle (from a second host
+ * thread) is refused with NNP_E_STATE before it reads or writes any of the
+ * handle's state; nnp_last_error on that thread then names the cause, and the
+ * running call is unaffected (nnp_last_timings returns 0 and
+ * nnp_workspace_bytes -1 in that case).  Different handles may be used
+ * concurrently.  All work of a call is enqueued on the caller's stream; calls
+ * that return a host value (the energy) or detect errors synchronise that
+ * stream.
  */
 #ifndef NNP_H
 #define NNP_H
@@ -231,7 +237,8 @@ typedef enum { NNP_DERIV_RECOMPUTE = 0, NNP_DERIV_STORED = 1 } nnp_deriv_mode;
 nnp_status nnp_set_derivative_mode(nnp_handle* h, int mode);
 
 /* Device memory held by the handle's workspace, in bytes (grow-only buffers
- * kept until nnp_destroy; excludes the parameter and table blocks). */
+ * kept until nnp_destroy; excludes the parameter and table blocks); -1 while
+ * another call holds the handle. */
 int64_t nnp_workspace_bytes(const nnp_handle* h);
 
 /* Number of network parameters: sum over elements and layers of out*in + out. */
@@ -251,7 +258,7 @@ nnp_status nnp_get_params(const nnp_handle* h, double* flat_params_host);
  * Per-kernel timing of the last call on this handle, in milliseconds, from
  * HIP events on the caller's stream, when enabled with nnp_set_profiling.
  *  names: receives up to max_k static kernel-stage names; ms: their times.
- * Returns the number of stages written.
+ * Returns the number of stages written (0 while another call holds the handle).
  */
 nnp_status nnp_set_profiling(nnp_handle* h, int enable);
 int nnp_last_timings(const nnp_handle* h, const char** names, double* ms, int max_k);
@@ -283,7 +290,8 @@ nnp_status nnp_set_neighbor_capacity(nnp_handle* h, int cap);
 void nnp_destroy(nnp_handle* h);
 
 /* Readable message of the last error on this handle ("" if none); with a NULL
- * handle, the last error of nnp_create on this thread. */
+ * handle, the last error of nnp_create on this thread.  After a call on this
+ * thread was refused because the handle was busy, that refusal's message. */
 const char* nnp_last_error(const nnp_handle* h);
 
 #ifdef __cplusplus

@@ -2,6 +2,7 @@
 // SF table and networks into device blocks, the growable workspace, and the
 // kernel sequence of one call on the caller's stream.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -66,6 +67,7 @@ struct nnp_handle {
   int jac_cap = 0;
   std::vector<int64_t> jac_offs;
   std::vector<double> jac_boxes;
+  std::atomic<int> busy{0};              // an ABI call is running on this handle
 };
 
 namespace nnp {
@@ -76,6 +78,35 @@ nnp_status fail(nnp_handle* h, nnp_status st, const std::string& msg) {
   else g_create_error = msg;
   return st;
 }
+
+// A call refused because its handle was busy reports through these (per host
+// thread): the running call owns the handle's own message.
+thread_local const nnp_handle* t_busy_handle = nullptr;
+thread_local std::string t_busy_error;
+
+// Holds the handle for the duration of one ABI call.  A call that overlaps
+// another on the same handle (from a second host thread) is refused with
+// NNP_E_STATE before it reads or writes any of the handle's state.
+struct Claim {
+  nnp_handle* h;
+  bool ok;
+  explicit Claim(nnp_handle* h_) : h(h_) {
+    int idle = 0;
+    ok = h->busy.compare_exchange_strong(idle, 1, std::memory_order_acquire);
+    if (ok) {
+      t_busy_handle = nullptr;
+      h->err.clear();
+    } else {
+      t_busy_handle = h;
+      t_busy_error = "the handle is in use by another call (one host thread and one stream at a time)";
+    }
+  }
+  ~Claim() {
+    if (ok) h->busy.store(0, std::memory_order_release);
+  }
+  Claim(const Claim&) = delete;
+  Claim& operator=(const Claim&) = delete;
+};
 
 #define NNP_HIP(h, call)                                                                             \
   do {                                                                                                \
@@ -979,7 +1010,8 @@ nnp_status nnp_create(int n_el, const char* const* elements, int n_sf, const nnp
 nnp_status nnp_count_work(nnp_handle* h, int64_t n_atoms, const void* pos, const int32_t* types, const double box[3],
                           int64_t counts[5], void* stream) {
   if (!h) return NNP_E_ARG;
-  h->err.clear();
+  Claim claim(h);
+  if (!claim.ok) return NNP_E_STATE;
   if (!counts || !box || n_atoms < 0) return fail(h, NNP_E_ARG, "bad arguments");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int64_t offs[2] = {0, n_atoms};
@@ -1025,7 +1057,8 @@ nnp_status nnp_compute_batch(nnp_handle* h, int n_struct, const int64_t* atom_of
                              const int32_t* types, const double* boxes, double* energies, void* atom_energy,
                              void* forces, void* stream) {
   if (!h) return NNP_E_ARG;
-  h->err.clear();
+  Claim claim(h);
+  if (!claim.ok) return NNP_E_STATE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   switch (h->prec) {
     case NNP_FP64: return forward<P_FP64>(h, n_struct, atom_offsets, pos, types, boxes, energies, nullptr, atom_energy, forces, s);
@@ -1037,7 +1070,8 @@ nnp_status nnp_compute_batch(nnp_handle* h, int n_struct, const int64_t* atom_of
 nnp_status nnp_compute(nnp_handle* h, int64_t n_atoms, const void* pos, const int32_t* types, const double box[3],
                        double* energy, void* atom_energy, void* forces, void* stream) {
   if (!h) return NNP_E_ARG;
-  h->err.clear();
+  Claim claim(h);
+  if (!claim.ok) return NNP_E_STATE;
   if (n_atoms < 0) return fail(h, NNP_E_ARG, "n_atoms must be >= 0");
   if (!box) return fail(h, NNP_E_ARG, "box must not be NULL");
   const int64_t offs[2] = {0, n_atoms};
@@ -1057,7 +1091,8 @@ nnp_status nnp_backward(nnp_handle* h, int n_struct, const int64_t* atom_offsets
                         const int32_t* types, const double* boxes, const double* dL_dE, const void* dL_dF,
                         void* grad_params, void* stream) {
   if (!h) return NNP_E_ARG;
-  h->err.clear();
+  Claim claim(h);
+  if (!claim.ok) return NNP_E_STATE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   switch (h->prec) {
     case NNP_FP64: return backward<P_FP64>(h, n_struct, atom_offsets, pos, types, boxes, dL_dE, dL_dF, (double*)grad_params, s);
@@ -1070,7 +1105,8 @@ int64_t nnp_n_params(const nnp_handle* h) { return h ? (int64_t)h->params.size()
 
 nnp_status nnp_set_params(nnp_handle* h, const void* flat, int on_device) {
   if (!h) return NNP_E_ARG;
-  h->err.clear();
+  Claim claim(h);
+  if (!claim.ok) return NNP_E_STATE;
   if (!flat) return fail(h, NNP_E_ARG, "flat_params must not be NULL");
   std::vector<double> p(h->params.size());
   if (on_device) {
@@ -1087,18 +1123,24 @@ nnp_status nnp_set_params(nnp_handle* h, const void* flat, int on_device) {
 
 nnp_status nnp_get_params(const nnp_handle* h, double* out) {
   if (!h || !out) return NNP_E_ARG;
+  Claim claim(const_cast<nnp_handle*>(h));
+  if (!claim.ok) return NNP_E_STATE;
   std::memcpy(out, h->params.data(), h->params.size() * sizeof(double));
   return NNP_OK;
 }
 
 nnp_status nnp_set_profiling(nnp_handle* h, int enable) {
   if (!h) return NNP_E_ARG;
+  Claim claim(h);
+  if (!claim.ok) return NNP_E_STATE;
   h->prof = enable != 0;
   return NNP_OK;
 }
 
 int nnp_last_timings(const nnp_handle* h, const char** names, double* ms, int max_k) {
   if (!h) return 0;
+  Claim claim(const_cast<nnp_handle*>(h));
+  if (!claim.ok) return 0;
   const int k = std::min<int>(max_k, (int)h->t_ms.size());
   for (int i = 0; i < k; ++i) {
     if (names) names[i] = h->t_names[i];
@@ -1111,7 +1153,8 @@ nnp_status nnp_md_run(nnp_handle* h, int64_t n_atoms, void* pos, void* vel, void
                       const double box[3], const double* masses, double dt_fs, int n_steps, double* epot,
                       double* ekin, void* stream) {
   if (!h) return NNP_E_ARG;
-  h->err.clear();
+  Claim claim(h);
+  if (!claim.ok) return NNP_E_STATE;
   if (n_atoms < 0 || n_steps < 0) return fail(h, NNP_E_ARG, "n_atoms and n_steps must be >= 0");
   if (n_atoms > 0 && (!pos || !vel || !forces || !types))
     return fail(h, NNP_E_ARG, "pos, vel, forces and types must not be NULL");
@@ -1129,7 +1172,8 @@ nnp_status nnp_md_run(nnp_handle* h, int64_t n_atoms, void* pos, void* vel, void
 
 nnp_status nnp_set_parallelism(nnp_handle* h, int mode) {
   if (!h) return NNP_E_ARG;
-  h->err.clear();
+  Claim claim(h);
+  if (!claim.ok) return NNP_E_STATE;
   if (mode != NNP_PAR_AUTO && mode != NNP_PAR_WAVE && mode != NNP_PAR_THREAD)
     return fail(h, NNP_E_ARG, "parallelism must be NNP_PAR_AUTO, NNP_PAR_WAVE or NNP_PAR_THREAD");
   h->parallelism = mode;
@@ -1138,7 +1182,8 @@ nnp_status nnp_set_parallelism(nnp_handle* h, int mode) {
 
 nnp_status nnp_set_derivative_mode(nnp_handle* h, int mode) {
   if (!h) return NNP_E_ARG;
-  h->err.clear();
+  Claim claim(h);
+  if (!claim.ok) return NNP_E_STATE;
   if (mode != NNP_DERIV_RECOMPUTE && mode != NNP_DERIV_STORED)
     return fail(h, NNP_E_ARG, "derivative mode must be NNP_DERIV_RECOMPUTE or NNP_DERIV_STORED");
   if (mode == NNP_DERIV_STORED && h->prec == NNP_BF16_MIXED)
@@ -1150,6 +1195,8 @@ nnp_status nnp_set_derivative_mode(nnp_handle* h, int mode) {
 
 int64_t nnp_workspace_bytes(const nnp_handle* h) {
   if (!h) return 0;
+  Claim claim(const_cast<nnp_handle*>(h));
+  if (!claim.ok) return -1;
   int64_t b = 0;
   for (const auto& kv : h->ws) b += (int64_t)kv.second.bytes;
   return b;
@@ -1159,6 +1206,8 @@ int nnp_neighbor_capacity(const nnp_handle* h) { return h ? h->cap : 0; }
 
 nnp_status nnp_set_neighbor_capacity(nnp_handle* h, int cap) {
   if (!h) return NNP_E_ARG;
+  Claim claim(h);
+  if (!claim.ok) return NNP_E_STATE;
   if (cap < 8) return fail(h, NNP_E_ARG, "capacity must be >= 8");
   h->cap_override = cap;
   h->cap = cap;
@@ -1180,6 +1229,10 @@ void nnp_destroy(nnp_handle* h) {
   delete h;
 }
 
-const char* nnp_last_error(const nnp_handle* h) { return h ? h->err.c_str() : nnp::g_create_error.c_str(); }
+const char* nnp_last_error(const nnp_handle* h) {
+  if (!h) return nnp::g_create_error.c_str();
+  if (h == nnp::t_busy_handle) return nnp::t_busy_error.c_str();
+  return h->err.c_str();
+}
 
 }  // extern "C"

@@ -206,3 +206,58 @@ def test_count_work_matches_brute_force(pots):
         say(prec, "count_work", got)
         assert got == {"pairs": pairs, "candidates": cand, "triplets": trip, "angular_terms": aterms,
                        "radial_terms": rterms}
+
+
+def test_overlapping_call_on_one_handle_is_refused():
+    """While an MD run holds a handle (from a second host thread), a call on the
+    same handle is refused with NNP_E_STATE and a message on the calling
+    thread; the running call completes intact, a second handle works
+    meanwhile, and the first handle works again afterwards."""
+    import threading
+    import time
+
+    import torch
+
+    from paper_2002_00054_amd.nnp import NNPError
+
+    pot = make_potential("fp64")
+    b = synth.water_box(16, 11)
+    pos, types = to_dev(b, torch.float64)
+    x = pos.clone()
+    v = torch.zeros_like(pos)
+    out = {}
+
+    def md():
+        # a refusal here only means a poll below held the handle at this instant
+        for _ in range(1000):
+            try:
+                out["md"] = pot.md_run(x, v, types, b.box, synth.WATER_MASSES, 0.25, 1500)
+                return
+            except NNPError as e:
+                if e.status != -6:
+                    out["err"] = e
+                    return
+                time.sleep(0.001)
+        out["err"] = RuntimeError("the MD run never got the handle")
+
+    th = threading.Thread(target=md)
+    th.start()
+    deadline = time.time() + 60.0
+    while pot.workspace_bytes != -1 and "md" not in out and time.time() < deadline:
+        time.sleep(0.0005)
+    assert "md" not in out and "err" not in out, "the MD run ended before it was seen holding the handle"
+    with pytest.raises(NNPError, match=r"NNP_E_STATE: the handle is in use"):
+        pot.compute(pos, types, b.box)
+    other = make_potential("fp64")
+    e2, ei2, f2 = run(other, synth.water_box(4, 1))
+    th.join()
+    assert "err" not in out, out.get("err")
+    f, ep, ek = out["md"]
+    assert np.all(np.isfinite(ep)) and np.all(np.isfinite(ek)) and len(ep) == 1501
+    ref = oracle_water().compute(synth.water_box(4, 1).pos, synth.water_box(4, 1).types, synth.water_box(4, 1).box)
+    check_fp64(ei2, f2, ref["Ei"], ref["F"])
+    e, ei, fr = run(pot, b)
+    e_fresh, _, _ = run(other, b)
+    assert e == e_fresh
+    other.close()
+    pot.close()
