@@ -100,7 +100,7 @@ def cpu_baseline(table, nets, budget_s=12.0, nthreads=0, workload="water"):
     }
 
 
-def report(table, nets):
+def report(table, nets, sections=None):
     """Extra JSON lines instead of the contract line: the measured device peaks,
     every form over the size sweep, the single-element fcc workload (3.9 A
     cutoff, up to 1,492,992 atoms; narrow and wide angular SFs), the two
@@ -108,7 +108,9 @@ def report(table, nets):
     form (32 uneven boxes, loss = energy MSE + 0.1 force MSE, synthetic
     targets) with recomputed and with stored SF derivatives, the forward with
     each, velocity Verlet MD steps (throughput and energy drift), and the CPU
-    oracle on one thread and on all threads."""
+    oracle on one thread and on all threads.  `sections` (a set of the line
+    names: peaks, sweep, training, ni, ni_g9, parallelism, forward_derivatives,
+    md, cpu_baseline) limits the report to those lines; None runs them all."""
     import numpy as np
     import torch
 
@@ -116,8 +118,13 @@ def report(table, nets):
     from paper_2002_00054_amd.nnp import Potential, energy_forces
 
     dev = torch.device("cuda:0")
-    print(json.dumps({"report": "peaks", **peaks.measure()}), flush=True)
-    for form in ("fp32", "fp64", "bf16"):
+
+    def want(name):
+        return sections is None or name in sections
+
+    if want("peaks"):
+        print(json.dumps({"report": "peaks", **peaks.measure()}), flush=True)
+    for form in (("fp32", "fp64", "bf16") if want("sweep") else ()):
         pot = Potential(table, nets, precision=form)
         for side in (16, 32, 44, 64, 88):
             bb = synth.water_box(side, 22)
@@ -130,45 +137,46 @@ def report(table, nets):
         pot.close()
         torch.cuda.empty_cache()
     # differentiation form: one training step = forward of the batch + loss + weight gradient
-    boxes = synth.training_batch()
-    offs = np.cumsum([0] + [bx.n_atoms for bx in boxes])
-    bxs = np.stack([bx.box for bx in boxes])
-    rng = np.random.default_rng(5)
-    N = torch.tensor([bx.n_atoms for bx in boxes], dtype=torch.float64, device=dev)
-    Eh = torch.tensor(rng.normal(-1.5, 0.1, len(boxes)) * N.cpu().numpy(), dtype=torch.float64, device=dev)
-    Fhat = rng.normal(0.0, 1.0, (int(offs[-1]), 3))
-    for form, mode in (("fp32", "recompute"), ("fp32", "stored"), ("fp64", "recompute"), ("fp64", "stored")):
-        pot = Potential(table, nets, precision=form)
-        pot.set_derivative_mode(mode)
-        pos = torch.tensor(np.concatenate([bx.pos for bx in boxes]), dtype=pot.dtype, device=dev)
-        t = torch.tensor(np.concatenate([bx.types for bx in boxes]), dtype=torch.int32, device=dev)
-        Fh = torch.tensor(Fhat, dtype=pot.dtype, device=dev)
-        th = torch.tensor(synth.flat_params(nets), dtype=torch.float64, device=dev, requires_grad=True)
+    if want("training"):
+        boxes = synth.training_batch()
+        offs = np.cumsum([0] + [bx.n_atoms for bx in boxes])
+        bxs = np.stack([bx.box for bx in boxes])
+        rng = np.random.default_rng(5)
+        N = torch.tensor([bx.n_atoms for bx in boxes], dtype=torch.float64, device=dev)
+        Eh = torch.tensor(rng.normal(-1.5, 0.1, len(boxes)) * N.cpu().numpy(), dtype=torch.float64, device=dev)
+        Fhat = rng.normal(0.0, 1.0, (int(offs[-1]), 3))
+        for form, mode in (("fp32", "recompute"), ("fp32", "stored"), ("fp64", "recompute"), ("fp64", "stored")):
+            pot = Potential(table, nets, precision=form)
+            pot.set_derivative_mode(mode)
+            pos = torch.tensor(np.concatenate([bx.pos for bx in boxes]), dtype=pot.dtype, device=dev)
+            t = torch.tensor(np.concatenate([bx.types for bx in boxes]), dtype=torch.int32, device=dev)
+            Fh = torch.tensor(Fhat, dtype=pot.dtype, device=dev)
+            th = torch.tensor(synth.flat_params(nets), dtype=torch.float64, device=dev, requires_grad=True)
 
-        def step():
-            E, F = energy_forces(th, pos, pot, t, offs, bxs)
-            L = torch.mean(((E - Eh) / N) ** 2) + 0.1 * torch.sum((F - Fh).double() ** 2) / (3 * N.sum())
-            (g,) = torch.autograd.grad(L, th)
-            return g
+            def step():
+                E, F = energy_forces(th, pos, pot, t, offs, bxs)
+                L = torch.mean(((E - Eh) / N) ** 2) + 0.1 * torch.sum((F - Fh).double() ** 2) / (3 * N.sum())
+                (g,) = torch.autograd.grad(L, th)
+                return g
 
-        for _ in range(2):
-            step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(5):
-            step()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / 5
-        print(json.dumps({"report": "training", "form": form, "derivatives": mode, "boxes": len(boxes),
-                          "atoms": int(offs[-1]), "ms_per_step": dt * 1e3,
-                          "workspace_gb": pot.workspace_bytes / 1e9}), flush=True)
-        pot.close()
-        torch.cuda.empty_cache()
+            for _ in range(2):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                step()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 5
+            print(json.dumps({"report": "training", "form": form, "derivatives": mode, "boxes": len(boxes),
+                              "atoms": int(offs[-1]), "ms_per_step": dt * 1e3,
+                              "workspace_gb": pot.workspace_bytes / 1e9}), flush=True)
+            pot.close()
+            torch.cuda.empty_cache()
     # second workload: single-element fcc metal, 3.9 A cutoff (the paper's Ni runs: ~1.5M atoms)
     from paper_2002_00054_amd import opcount
 
     ni_table, ni_nets = synth.ni_table_scaled(), synth.ni_nets()
-    for form in ("fp32", "fp64", "bf16"):
+    for form in (("fp32", "fp64", "bf16") if want("ni") else ()):
         pot = Potential(ni_table, ni_nets, precision=form, elements=("Ni",))
         for side in ((20, 40, 72) if form == "fp32" else (72,)):
             bb = synth.fcc_box(side, side)
@@ -188,8 +196,8 @@ def report(table, nets):
         torch.cuda.empty_cache()
     # the fcc workload with wide angular functions G9 (thread-per-centre passes)
     g9_table = synth.ni_table_scaled(wide=True)
-    bb = synth.fcc_box(72, 72)
-    for form in ("fp32", "fp64"):
+    bb = synth.fcc_box(72, 72) if want("ni_g9") else None
+    for form in (("fp32", "fp64") if want("ni_g9") else ()):
         pot = Potential(g9_table, ni_nets, precision=form, elements=("Ni",))
         x = torch.tensor(bb.pos, dtype=pot.dtype, device=dev)
         t = torch.tensor(bb.types, dtype=torch.int32, device=dev)
@@ -200,8 +208,8 @@ def report(table, nets):
         del x, t
         torch.cuda.empty_cache()
     # level of parallelism of the SF and force passes: a wave per centre against a thread per centre
-    for wl, bb, tb, nt in (("ni", synth.fcc_box(72, 72), ni_table, ni_nets),
-                           ("water", synth.water_box(88, 22), table, nets)):
+    for wl, bb, tb, nt in ((("ni", synth.fcc_box(72, 72), ni_table, ni_nets),
+                            ("water", synth.water_box(88, 22), table, nets)) if want("parallelism") else ()):
         for mode in ("wave", "thread"):
             pot = Potential(tb, nt, precision="fp32", elements=("Ni",) if wl == "ni" else ("H", "O"))
             pot.set_parallelism(mode)
@@ -214,8 +222,8 @@ def report(table, nets):
             del x, t
             torch.cuda.empty_cache()
     # one energy+force evaluation with the stored-Jacobian forward (one eighth of the 2M box)
-    bb = synth.water_box(44, 22)
-    for mode in ("recompute", "stored"):
+    bb = synth.water_box(44, 22) if want("forward_derivatives") else None
+    for mode in (("recompute", "stored") if want("forward_derivatives") else ()):
         pot = Potential(table, nets, precision="fp32")
         pot.set_derivative_mode(mode)
         x = torch.tensor(bb.pos, dtype=torch.float32, device=dev)
@@ -228,7 +236,7 @@ def report(table, nets):
         del x, t
         torch.cuda.empty_cache()
     # MD driver: velocity Verlet steps of the 2M box (FP32) and of a 12,288-atom box (FP64)
-    for side, seed, form, dt, steps in ((88, 22, "fp32", 0.5, 30), (16, 12, "fp64", 0.25, 200)):
+    for side, seed, form, dt, steps in (((88, 22, "fp32", 0.5, 30), (16, 12, "fp64", 0.25, 200)) if want("md") else ()):
         bb = synth.water_box(side, seed)
         pot = Potential(table, nets, precision=form)
         x = torch.tensor(bb.pos, dtype=pot.dtype, device=dev)
@@ -247,7 +255,7 @@ def report(table, nets):
         pot.close()
         del x, v, t
         torch.cuda.empty_cache()
-    for nt in (0, 1):  # all threads first: a thread count set once stays set
+    for nt in ((0, 1) if want("cpu_baseline") else ()):  # all threads first: a thread count set once stays set
         cb = cpu_baseline(table, nets, budget_s=30.0 if nt == 1 else 12.0, nthreads=nt)
         print(json.dumps({"report": "cpu_baseline", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
                           **cb}), flush=True)
@@ -267,6 +275,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--report", action="store_true",
                     help="print only the peaks / size-sweep / training / CPU report lines")
+    ap.add_argument("--sections", default=None,
+                    help="with --report: comma list of report lines to run (peaks, sweep, training, ni, ni_g9, "
+                         "parallelism, forward_derivatives, md, cpu_baseline); default all")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB with a plain device copy (for HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -292,7 +303,12 @@ def main():
 
     table, nets = synth.water_table_scaled(), synth.water_nets()
     if args.report:
-        report(table, nets)
+        known = {"peaks", "sweep", "training", "ni", "ni_g9", "parallelism", "forward_derivatives", "md",
+                 "cpu_baseline"}
+        sections = None if args.sections is None else {x for x in args.sections.split(",") if x}
+        if sections is not None and not sections <= known:
+            ap.error(f"unknown report sections {sorted(sections - known)}; known: {sorted(known)}")
+        report(table, nets, sections)
         return
     water = args.workload == "water"
     if args.n_side is None:
