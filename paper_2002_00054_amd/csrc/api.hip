@@ -397,6 +397,7 @@ nnp_status prepare(nnp_handle* h, Common& cm, const IO* pos, const int32_t* type
   if ((st = ensure_t(h, "cursor", nkeys + 1, &a.cursor))) return st;
   if ((st = ensure_t(h, "scan", nkeys / 4096 + 1, &a.scan))) return st;
   if ((st = ensure_t(h, "perm", std::max<int64_t>(n, 1), &a.perm))) return st;
+  if ((st = ensure_t(h, "perm_raw", std::max<int64_t>(n, 1), &a.perm_raw))) return st;
   if ((st = ensure_t(h, "pos4", std::max<int64_t>(n, 1), &a.pos4))) return st;
   if ((st = ensure_t(h, "eoff", MAX_EL + 1, &a.eoff))) return st;
   if ((st = ensure_t(h, "flags", 4, &a.flags))) return st;

@@ -150,20 +150,21 @@ __global__ void __launch_bounds__(256) k_scatter(int64_t n, const int* __restric
 
 // Within every bin, order atoms by caller index (the scatter's atomics leave
 // the order arbitrary; this makes the whole path deterministic up to the
-// force atomics).
-__global__ void __launch_bounds__(256) k_sort_bins(int nkeys, const int* __restrict__ start, int* __restrict__ perm) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nkeys) return;
+// force atomics).  One thread per atom, out of place (raw -> perm): the atom
+// the scatter put at slot s of its bin goes to the bin's start plus the
+// number of atoms of the bin with a smaller index (indices are distinct), so
+// every place lies in the bin and each is written once.
+__global__ void __launch_bounds__(256) k_sort_bins(int64_t n, const int* __restrict__ key,
+                                                   const int* __restrict__ start, const int* __restrict__ raw,
+                                                   int* __restrict__ perm) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int v = raw[s];
+  const int k = key[v];
   const int b = start[k], e = start[k + 1];
-  for (int i = b + 1; i < e; ++i) {
-    const int v = perm[i];
-    int j = i - 1;
-    while (j >= b && perm[j] > v) {
-      perm[j + 1] = perm[j];
-      --j;
-    }
-    perm[j + 1] = v;
-  }
+  int place = b;
+  for (int j = b; j < e; ++j) place += raw[j] < v ? 1 : 0;
+  perm[place] = v;
 }
 
 // Sorted FP64 positions (wrapped) with the packed element / structure id.
@@ -478,8 +479,8 @@ void launch_bin_sort(const BinArgs& a, const TIn* pos, hipStream_t stream) {
   hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, stream, nkeys, a.count, a.scan, a.start, a.cursor);
   if (n > 0) {
     const unsigned g = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, stream, n, a.key, a.cursor, a.perm);
-    hipLaunchKernelGGL(k_sort_bins, dim3((nkeys + 255) / 256), dim3(256), 0, stream, nkeys, a.start, a.perm);
+    hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, stream, n, a.key, a.cursor, a.perm_raw);
+    hipLaunchKernelGGL(k_sort_bins, dim3(g), dim3(256), 0, stream, n, a.key, a.start, a.perm_raw, a.perm);
     hipLaunchKernelGGL(k_fill_sorted<TIn>, dim3(g), dim3(256), 0, stream, n, pos, a.types, a.st, a.soff,
                        a.n_struct, a.n_el, a.perm, a.pos4);
   }

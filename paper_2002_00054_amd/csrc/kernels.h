@@ -20,6 +20,7 @@ struct BinArgs {
   int* cursor;               // [n_el * total_cells + 1]
   int* scan;                 // [ceil((n_el * total_cells) / 4096)] block sums of the scan
   int* perm;                 // [n] sorted -> caller index
+  int* perm_raw;             // [n] the scatter's order within each bin, before the bin sort
   double4* pos4;             // [n] sorted wrapped positions + ids
   int* eoff;                 // [n_el + 1] element offsets of the sorted order
   int* flags;                // [0] bad type, [1] max neighbour count beyond cap, [2] max count
