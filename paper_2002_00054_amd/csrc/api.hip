@@ -680,7 +680,9 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
   double *gE_atom, *part, *padded;
   T* vec;
   const int64_t n1 = std::max<int64_t>(n, 1);
-  const int chunk = 256;
+  // atoms per chunk of the weight-gradient reduction: 64, or more once there
+  // would be over 4096 chunks (bounds the FP64 partial sums)
+  const int chunk = (int)std::max<int64_t>(64, (n1 + 4095) / 4096);
   const int nch = (int)((n1 + chunk - 1) / chunk);
   if ((st = ensure_t(h, "G", (size_t)n1 * LD, &G))) return st;
   if ((st = ensure_t(h, "V", (size_t)n1 * LD, &V))) return st;

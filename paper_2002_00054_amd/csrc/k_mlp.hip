@@ -277,53 +277,97 @@ __global__ void __launch_bounds__(256) k_wgrad_atoms(WGradArgs<P> a) {
   out[10 * HID] = alpha;
 }
 
+template <class T> struct PairOf;
+template <> struct PairOf<float> { using type = float2; };
+template <> struct PairOf<double> { using type = double2; };
+
 // partial[(e * nch + ch) * NET_STRIDE + p]: sum over one chunk of atoms of
-// element e of the per-atom gradient of parameter p (padded layout).
+// element e of the per-atom gradient of every parameter p (padded layout), in
+// FP64.  One 256-thread block per (chunk, element) covers all parameters, so
+// each atom's vector is read once per chunk.  The weight gradients are outer
+// products (W1: zb1 x^T + dzb1 t^T, W2: zb2 h1^T + dzb2 dh1^T): thread t owns
+// the 2 x 2 tile at (o, k) = (2 (t / 16), 2 (t % 16)) of both matrices and
+// reads four pairs of each per atom.  Threads 0-31 also own b1, b2 and w3 at
+// index t, thread 32 owns b3, and threads 33-63 write the padding (zero).
 template <class T>
 __global__ void __launch_bounds__(256) k_wgrad_chunks(const int* __restrict__ eoff, int chunk, int nch,
                                                       const T* __restrict__ vec, double* __restrict__ partial) {
-  const int e = blockIdx.z;
-  const int ch = blockIdx.y;
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= NET_STRIDE) return;
+  using T2 = typename PairOf<T>::type;
+  static_assert(HID == 32 && NET_STRIDE == OFF_B3 + HID, "tile map covers the padded layout exactly");
+  const int e = blockIdx.y;
+  const int ch = blockIdx.x;
+  const int t = threadIdx.x;
+  const int o0 = 2 * (t >> 4), k0 = 2 * (t & 15);
   const int64_t lo = eoff[e] + (int64_t)ch * chunk;
   const int64_t hi = min((int64_t)eoff[e + 1], lo + chunk);
-  double s = 0.0;
+  double w1[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, w2[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  double b1 = 0.0, b2 = 0.0, w3 = 0.0, b3 = 0.0;
   for (int64_t r = lo; r < hi; ++r) {
     const T* v = vec + r * (WG_VEC * HID);
-    T g;
-    if (p < OFF_B1) {  // W1[o][k]: zb1[o] x[k] + dzb1[o] t[k]
-      const int o = p / HID, k = p % HID;
-      g = v[4 * HID + o] * v[0 * HID + k] + v[5 * HID + o] * v[1 * HID + k];
-    } else if (p < OFF_W2) {
-      g = v[4 * HID + (p - OFF_B1)];
-    } else if (p < OFF_B2) {  // W2[o][k]: zb2[o] h1[k] + dzb2[o] dh1[k]
-      const int q = p - OFF_W2, o = q / HID, k = q % HID;
-      g = v[8 * HID + o] * v[2 * HID + k] + v[9 * HID + o] * v[3 * HID + k];
-    } else if (p < OFF_W3) {
-      g = v[8 * HID + (p - OFF_B2)];
-    } else if (p < OFF_B3) {  // w3[o]: alpha h2[o] - dh2[o]
-      const int o = p - OFF_W3;
-      g = v[10 * HID] * v[6 * HID + o] - v[7 * HID + o];
-    } else if (p == OFF_B3) {
-      g = v[10 * HID];
-    } else {
-      g = T(0);
+    const T2 zb1 = *reinterpret_cast<const T2*>(v + 4 * HID + o0);
+    const T2 dzb1 = *reinterpret_cast<const T2*>(v + 5 * HID + o0);
+    const T2 x = *reinterpret_cast<const T2*>(v + 0 * HID + k0);
+    const T2 tg = *reinterpret_cast<const T2*>(v + 1 * HID + k0);
+    const T2 zb2 = *reinterpret_cast<const T2*>(v + 8 * HID + o0);
+    const T2 dzb2 = *reinterpret_cast<const T2*>(v + 9 * HID + o0);
+    const T2 h1 = *reinterpret_cast<const T2*>(v + 2 * HID + k0);
+    const T2 dh1 = *reinterpret_cast<const T2*>(v + 3 * HID + k0);
+    const T a_o[2] = {zb1.x, zb1.y}, c_o[2] = {dzb1.x, dzb1.y}, b_k[2] = {x.x, x.y}, d_k[2] = {tg.x, tg.y};
+    const T p_o[2] = {zb2.x, zb2.y}, q_o[2] = {dzb2.x, dzb2.y}, u_k[2] = {h1.x, h1.y}, w_k[2] = {dh1.x, dh1.y};
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        w1[i][j] += (double)(a_o[i] * b_k[j] + c_o[i] * d_k[j]);
+        w2[i][j] += (double)(p_o[i] * u_k[j] + q_o[i] * w_k[j]);
+      }
+    if (t < HID) {
+      b1 += (double)v[4 * HID + t];
+      b2 += (double)v[8 * HID + t];
+      w3 += (double)(v[10 * HID] * v[6 * HID + t] - v[7 * HID + t]);
+    } else if (t == HID) {
+      b3 += (double)v[10 * HID];
     }
-    s += (double)g;
   }
-  partial[((size_t)e * nch + ch) * NET_STRIDE + p] = s;
+  double* out = partial + ((size_t)e * nch + ch) * NET_STRIDE;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      out[OFF_W1 + (o0 + i) * HID + k0 + j] = w1[i][j];
+      out[OFF_W2 + (o0 + i) * HID + k0 + j] = w2[i][j];
+    }
+  if (t < HID) {
+    out[OFF_B1 + t] = b1;
+    out[OFF_B2 + t] = b2;
+    out[OFF_W3 + t] = w3;
+  } else if (t == HID) {
+    out[OFF_B3] = b3;
+  } else if (t < 2 * HID) {
+    out[OFF_B3 + (t - HID)] = 0.0;
+  }
 }
 
-// out[e][p] = sum over the chunks of element e in chunk order (FP64).
+// out[e][p] = sum over the chunks of element e (FP64) in a fixed order: eight
+// running sums, chunk ch going to sum ch % 8 in chunk order, then the eight
+// in order.  A block covers 32 parameters with 8 threads each.
 __global__ void __launch_bounds__(256) k_wgrad_final(int nch, const double* __restrict__ partial,
                                                      double* __restrict__ out) {
+  __shared__ double red[8][32];
   const int e = blockIdx.y;
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= NET_STRIDE) return;
+  const int pl = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const int p = blockIdx.x * 32 + pl;
   double s = 0.0;
-  for (int ch = 0; ch < nch; ++ch) s += partial[((size_t)e * nch + ch) * NET_STRIDE + p];
-  out[(size_t)e * NET_STRIDE + p] = s;
+  if (p < NET_STRIDE)
+    for (int ch = g; ch < nch; ch += 8) s += partial[((size_t)e * nch + ch) * NET_STRIDE + p];
+  red[g][pl] = s;
+  __syncthreads();
+  if (g == 0 && p < NET_STRIDE) {
+    double tot = 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) tot += red[i][pl];
+    out[(size_t)e * NET_STRIDE + p] = tot;
+  }
 }
 
 // Padded gradient -> caller's flat parameter layout.
@@ -336,14 +380,14 @@ __global__ void __launch_bounds__(256) k_unpad(int64_t np, const int* __restrict
 template <int P>
 void launch_wgrad(const WGradArgs<P>& a, hipStream_t stream) {
   using T = typename Types<P>::T;
-  const unsigned gx = (NET_STRIDE + 255) / 256;
   if (a.n > 0) {
     const unsigned g = (unsigned)((a.n + 255) / 256 + a.n_el);
     hipLaunchKernelGGL(k_wgrad_atoms<P>, dim3(g), dim3(256), 0, stream, a);
   }
-  hipLaunchKernelGGL(k_wgrad_chunks<T>, dim3(gx, a.nch, a.n_el), dim3(256), 0, stream, a.eoff, a.chunk, a.nch,
+  hipLaunchKernelGGL(k_wgrad_chunks<T>, dim3((unsigned)a.nch, a.n_el), dim3(256), 0, stream, a.eoff, a.chunk, a.nch,
                      (const T*)a.vec, a.partial);
-  hipLaunchKernelGGL(k_wgrad_final, dim3(gx, a.n_el), dim3(256), 0, stream, a.nch, a.partial, a.padded);
+  hipLaunchKernelGGL(k_wgrad_final, dim3((NET_STRIDE + 31) / 32, a.n_el), dim3(256), 0, stream, a.nch, a.partial,
+                     a.padded);
   hipLaunchKernelGGL(k_unpad, dim3((unsigned)((a.n_params + 255) / 256)), dim3(256), 0, stream, a.n_params, a.flatmap,
                      a.padded, a.out);
 }
