@@ -283,7 +283,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the spatial decomposition "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the spatial decomposition "
               "over several GPUs is a design note, not code); use --gpus 1", file=sys.stderr, flush=True)
         sys.exit(2)
 
