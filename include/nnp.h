@@ -32,8 +32,8 @@
  * running call is unaffected (nnp_last_timings returns 0 and
  * nnp_workspace_bytes -1 in that case).  Different handles may be used
  * concurrently.  All work of a call is enqueued on the caller's stream; calls
- * that return a host value (the energy) or detect errors synchronise that
- * stream.
+ * that return a host value (the energy) synchronise that stream; the others
+ * return with their device outputs ready in the stream's order.
  */
 #ifndef NNP_H
 #define NNP_H
@@ -153,7 +153,10 @@ nnp_status nnp_compute(nnp_handle* h, int64_t n_atoms, const void* pos, const in
  *  boxes         host double [n_struct][3]
  *  energies      device double [n_struct]; may be NULL
  *  atom_energy, forces  as in nnp_compute (batch order); may be NULL
- * Synchronises the stream. */
+ * Returns once the neighbour list is checked (the stream is synchronised
+ * for that) and the remaining kernels are enqueued: the device outputs are
+ * ready in the order of `stream` (read them on that stream, or after
+ * synchronising it).  With profiling on, the call synchronises at the end. */
 nnp_status nnp_compute_batch(nnp_handle* h, int n_struct, const int64_t* atom_offsets, const void* pos,
                              const int32_t* types, const double* boxes, double* energies,
                              void* atom_energy, void* forces, void* stream);
@@ -169,7 +172,8 @@ nnp_status nnp_compute_batch(nnp_handle* h, int n_struct, const int64_t* atom_of
  *  dL_dF        device [n_atoms][3] in the positions' type (may be NULL: no force term)
  *  grad_params  device double [nnp_n_params(h)], overwritten; flat layout of
  *               nnp_set_params
- * Synchronises the stream.  Errors as nnp_compute_batch. */
+ * Like nnp_compute_batch, returns with the gradient ready in the order of
+ * `stream`.  Errors as nnp_compute_batch. */
 nnp_status nnp_backward(nnp_handle* h, int n_struct, const int64_t* atom_offsets, const void* pos,
                         const int32_t* types, const double* boxes, const double* dL_dE,
                         const void* dL_dF, void* grad_params, void* stream);
@@ -247,7 +251,8 @@ int64_t nnp_n_params(const nnp_handle* h);
 /*
  * Replace every network parameter.  flat_params: double [nnp_n_params(h)],
  * element by element, layer by layer, W row-major [out][in] then b[out];
- * on_device != 0 if it is a device pointer (then the device is synchronised).
+ * on_device != 0 if it is a device pointer.  The device is synchronised first,
+ * so that kernels of earlier calls finish with the old parameters.
  */
 nnp_status nnp_set_params(nnp_handle* h, const void* flat_params, int on_device);
 

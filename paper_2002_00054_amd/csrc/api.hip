@@ -136,7 +136,9 @@ nnp_status ensure(nnp_handle* h, const char* name, size_t bytes, void** out) {
   DevBuf& b = h->ws[name];
   if (b.bytes < bytes) {
     if (b.p) {
-      hipError_t e = hipFree(b.p);
+      // an earlier call may have returned with kernels still using the buffer
+      hipError_t e = hipDeviceSynchronize();
+      if (e == hipSuccess) e = hipFree(b.p);
       b.p = nullptr;
       b.bytes = 0;
       if (e != hipSuccess) return fail(h, NNP_E_HIP, std::string("hipFree: ") + hipGetErrorString(e));
@@ -650,7 +652,9 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
       NNP_HIP(h, hipMemcpyAsync(h->h_energy, energies, sizeof(double), hipMemcpyDeviceToHost, stream));
     mk.mark("finish");
     if ((st = check_launch(h, "forward"))) return st;
-    NNP_HIP(h, hipStreamSynchronize(stream));
+    // Device outputs are ready in stream order; the host waits only for a
+    // host energy or for the profiling events.
+    if (energy_host || h->prof) NNP_HIP(h, hipStreamSynchronize(stream));
     if (energy_host) *energy_host = *h->h_energy;
     mk.finish();
     h->has_forward = true;
@@ -778,7 +782,8 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
   launch_wgrad<P>(wa, stream);
   mk.mark("wgrad");
   if ((st = check_launch(h, "backward"))) return st;
-  NNP_HIP(h, hipStreamSynchronize(stream));
+  // the gradient is ready in stream order; the host waits only for profiling
+  if (h->prof) NNP_HIP(h, hipStreamSynchronize(stream));
   mk.finish();
   h->jac_valid = stored;
   return NNP_OK;
@@ -1112,8 +1117,9 @@ nnp_status nnp_set_params(nnp_handle* h, const void* flat, int on_device) {
   if (!claim.ok) return NNP_E_STATE;
   if (!flat) return fail(h, NNP_E_ARG, "flat_params must not be NULL");
   std::vector<double> p(h->params.size());
+  // calls may return with kernels still reading the networks: let them finish
+  NNP_HIP(h, hipDeviceSynchronize());
   if (on_device) {
-    NNP_HIP(h, hipDeviceSynchronize());
     NNP_HIP(h, hipMemcpy(p.data(), flat, p.size() * sizeof(double), hipMemcpyDeviceToHost));
   } else {
     std::memcpy(p.data(), flat, p.size() * sizeof(double));
@@ -1220,6 +1226,7 @@ nnp_status nnp_set_neighbor_capacity(nnp_handle* h, int cap) {
 
 void nnp_destroy(nnp_handle* h) {
   if (!h) return;
+  (void)hipDeviceSynchronize();  // calls may return with kernels still using the workspace
   for (auto& kv : h->ws)
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (h->d_tab) (void)hipFree(h->d_tab);
