@@ -33,7 +33,9 @@
  * nnp_workspace_bytes -1 in that case).  Different handles may be used
  * concurrently.  All work of a call is enqueued on the caller's stream; calls
  * that return a host value (the energy) synchronise that stream; the others
- * return with their device outputs ready in the stream's order.
+ * return with their device outputs ready in the stream's order, and their
+ * last kernels may still be running: before using the handle on another
+ * stream, synchronise the first one.
  */
 #ifndef NNP_H
 #define NNP_H

@@ -362,28 +362,29 @@ nnp_status prepare(nnp_handle* h, Common& cm, const IO* pos, const int32_t* type
   const int nkeys = h->n_el * B.total_cells;
   nnp_status st;
   const size_t nst = B.st.size(), nso = B.soff.size(), nch = B.chunk_lo.size(), nsc = B.struct_chunk.size();
-  if ((st = ensure_t(h, "st", nst, &cm.d_st))) return st;
-  if ((st = ensure_t(h, "soff", nso, &cm.d_soff))) return st;
-  if ((st = ensure_t(h, "clo", std::max<size_t>(nch, 1), &cm.d_clo))) return st;
-  if ((st = ensure_t(h, "chi", std::max<size_t>(nch, 1), &cm.d_chi))) return st;
-  if ((st = ensure_t(h, "sc", nsc, &cm.d_sc))) return st;
-  const size_t bytes = nst * sizeof(DevStruct) + (nso + 2 * nch) * sizeof(int64_t) + nsc * sizeof(int) + 64;
+  // The batch description goes up in one copy: its five arrays are packed,
+  // 16-byte aligned, into one pinned staging block and one device block.
+  auto al = [](size_t b) { return (b + 15) & ~(size_t)15; };
+  const size_t o_st = 0, o_soff = o_st + al(nst * sizeof(DevStruct)), o_clo = o_soff + al(nso * sizeof(int64_t)),
+               o_chi = o_clo + al(std::max<size_t>(nch, 1) * sizeof(int64_t)),
+               o_sc = o_chi + al(std::max<size_t>(nch, 1) * sizeof(int64_t)), bytes = o_sc + al(nsc * sizeof(int));
+  unsigned char* d_desc = nullptr;
+  if ((st = ensure_t(h, "batch_desc", bytes, &d_desc))) return st;
   if ((st = stage(h, bytes))) return st;
   unsigned char* hs = (unsigned char*)h->h_stage;
-  size_t o = 0;
-  auto put = [&](void* dst, const void* src, size_t nbytes) -> hipError_t {
-    std::memcpy(hs + o, src, nbytes);
-    hipError_t e = hipMemcpyAsync(dst, hs + o, nbytes, hipMemcpyHostToDevice, stream);
-    o += (nbytes + 15) & ~(size_t)15;
-    return e;
-  };
-  NNP_HIP(h, put(cm.d_st, B.st.data(), nst * sizeof(DevStruct)));
-  NNP_HIP(h, put(cm.d_soff, B.soff.data(), nso * sizeof(int64_t)));
+  std::memcpy(hs + o_st, B.st.data(), nst * sizeof(DevStruct));
+  std::memcpy(hs + o_soff, B.soff.data(), nso * sizeof(int64_t));
   if (nch) {
-    NNP_HIP(h, put(cm.d_clo, B.chunk_lo.data(), nch * sizeof(int64_t)));
-    NNP_HIP(h, put(cm.d_chi, B.chunk_hi.data(), nch * sizeof(int64_t)));
+    std::memcpy(hs + o_clo, B.chunk_lo.data(), nch * sizeof(int64_t));
+    std::memcpy(hs + o_chi, B.chunk_hi.data(), nch * sizeof(int64_t));
   }
-  NNP_HIP(h, put(cm.d_sc, B.struct_chunk.data(), nsc * sizeof(int)));
+  std::memcpy(hs + o_sc, B.struct_chunk.data(), nsc * sizeof(int));
+  NNP_HIP(h, hipMemcpyAsync(d_desc, hs, bytes, hipMemcpyHostToDevice, stream));
+  cm.d_st = reinterpret_cast<DevStruct*>(d_desc + o_st);
+  cm.d_soff = reinterpret_cast<int64_t*>(d_desc + o_soff);
+  cm.d_clo = reinterpret_cast<int64_t*>(d_desc + o_clo);
+  cm.d_chi = reinterpret_cast<int64_t*>(d_desc + o_chi);
+  cm.d_sc = reinterpret_cast<int*>(d_desc + o_sc);
 
   BinArgs& a = cm.bin;
   a.n = n;
