@@ -204,77 +204,83 @@ void launch_mlp(const MlpArgs<P>& a, hipStream_t stream) {
 // adjoints of the pre-activations of the primal and tangent chains.
 constexpr int WG_VEC = 11;
 
+// One atom per 32 lanes (two per wave): lane l owns hidden unit l, so every
+// layer is one 32-term dot product per lane (a row of W, read four at a time)
+// whose inputs come from the atom's other lanes by width-32 shuffles; the
+// backward step through W2 has lane l own input l (a column of W2, read
+// coalesced across the lanes).  Same expressions and summation order as one
+// thread per atom, with 32 times the parallelism.
 template <int P>
 __global__ void __launch_bounds__(256) k_wgrad_atoms(WGradArgs<P> a) {
   using T = typename Types<P>::T;
+  using V4 = typename Vec4<T>::type;
+  constexpr int ATOMS = 256 / HID;  // atoms per block
   int e;
   int64_t r0, r1;
-  if (!element_tile(blockIdx.x, 256, a.n_el, a.eoff, e, r0, r1)) return;
+  if (!element_tile(blockIdx.x, ATOMS, a.n_el, a.eoff, e, r0, r1)) return;
   e = uniform(e);
-  const int64_t r = r0 + threadIdx.x;
-  if (r >= r1) return;
+  const int l = threadIdx.x & (HID - 1);
+  const int64_t r = r0 + (threadIdx.x / HID);
+  if (r >= r1) return;  // the atom's 32 lanes leave together
   const T* __restrict__ W = a.nets + (size_t)e * NET_STRIDE;
   T* out = a.vec + r * (WG_VEC * HID);
-  T x[HID], t[HID], h1[HID], dz1[HID];
+  const T x = (T)a.G[r * LD + l];
+  const T t = (T)a.V[r * LD + l] * (l < MAX_SF ? (T)a.tab->inv_scale_d[e][l] : T(0));
+  // layer 1: z = W1 x + b1 and its tangent W1 t (lane = output unit)
+  T z = W[OFF_B1 + l], dz = T(0);
 #pragma unroll
-  for (int k = 0; k < HID; ++k) {
-    x[k] = (T)a.G[r * LD + k];
-    t[k] = (T)a.V[r * LD + k] * (k < MAX_SF ? (T)a.tab->inv_scale_d[e][k] : T(0));
-  }
+  for (int kb = 0; kb < HID; kb += 4) {
+    const V4 w = *reinterpret_cast<const V4*>(W + OFF_W1 + l * HID + kb);
+    const T wk[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-  for (int o = 0; o < HID; ++o) {
-    T z = W[OFF_B1 + o], dz = T(0);
-#pragma unroll
-    for (int k = 0; k < HID; ++k) {
-      z += W[OFF_W1 + o * HID + k] * x[k];
-      dz += W[OFF_W1 + o * HID + k] * t[k];
+    for (int q = 0; q < 4; ++q) {
+      z += wk[q] * __shfl(x, kb + q, HID);
+      dz += wk[q] * __shfl(t, kb + q, HID);
     }
-    h1[o] = tanh_t(z);
-    dz1[o] = dz;
-    out[0 * HID + o] = x[o];
-    out[1 * HID + o] = t[o];
-    out[2 * HID + o] = h1[o];
-    out[3 * HID + o] = (T(1) - h1[o] * h1[o]) * dz;
   }
+  const T h1 = tanh_t(z), dz1 = dz;
+  const T dh1 = (T(1) - h1 * h1) * dz1;
+  out[0 * HID + l] = x;
+  out[1 * HID + l] = t;
+  out[2 * HID + l] = h1;
+  out[3 * HID + l] = dh1;
   const T alpha = a.gE_atom ? (T)a.gE_atom[r] : T(0);
-  // Objective J = alpha E - w3 . dh2, dh2 = (1 - h2^2) dz2.
-  T zb2[HID], dzb2[HID];
+  // layer 2.  Objective J = alpha E - w3 . dh2, dh2 = (1 - h2^2) dz2.
+  T z2 = W[OFF_B2 + l], dz2 = T(0);
+#pragma unroll
+  for (int kb = 0; kb < HID; kb += 4) {
+    const V4 w = *reinterpret_cast<const V4*>(W + OFF_W2 + l * HID + kb);
+    const T wk[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      z2 += wk[q] * __shfl(h1, kb + q, HID);
+      dz2 += wk[q] * __shfl(dh1, kb + q, HID);
+    }
+  }
+  const T h2 = tanh_t(z2);
+  const T g2 = T(1) - h2 * h2;
+  const T w3 = W[OFF_W3 + l];
+  // adjoint of h2: alpha w3 from E, and from -w3 . (1 - h2^2) dz2: +2 w3 h2 dz2
+  const T h2bar = alpha * w3 + T(2) * w3 * h2 * dz2;
+  const T zb2 = g2 * h2bar, dzb2 = -g2 * w3;
+  out[6 * HID + l] = h2;
+  out[7 * HID + l] = g2 * dz2;
+  out[8 * HID + l] = zb2;
+  out[9 * HID + l] = dzb2;
+  // back through W2 (lane = input unit of layer 2)
+  T hb = T(0), dhb = T(0);
 #pragma unroll
   for (int o = 0; o < HID; ++o) {
-    T z = W[OFF_B2 + o], dz = T(0);
-#pragma unroll
-    for (int k = 0; k < HID; ++k) {
-      const T w = W[OFF_W2 + o * HID + k];
-      z += w * h1[k];
-      dz += w * ((T(1) - h1[k] * h1[k]) * dz1[k]);
-    }
-    const T h2 = tanh_t(z);
-    const T g2 = T(1) - h2 * h2;
-    const T w3 = W[OFF_W3 + o];
-    // adjoint of h2: alpha w3 from E, and from -w3 . (1 - h2^2) dz2: +2 w3 h2 dz2
-    const T h2bar = alpha * w3 + T(2) * w3 * h2 * dz;
-    zb2[o] = g2 * h2bar;
-    dzb2[o] = -g2 * w3;
-    out[6 * HID + o] = h2;
-    out[7 * HID + o] = g2 * dz;
-    out[8 * HID + o] = zb2[o];
-    out[9 * HID + o] = dzb2[o];
+    const T w = W[OFF_W2 + o * HID + l];
+    hb += w * __shfl(zb2, o, HID);
+    dhb += w * __shfl(dzb2, o, HID);
   }
-#pragma unroll
-  for (int k = 0; k < HID; ++k) {
-    T hb = T(0), dhb = T(0);
-#pragma unroll
-    for (int o = 0; o < HID; ++o) {
-      hb += W[OFF_W2 + o * HID + k] * zb2[o];
-      dhb += W[OFF_W2 + o * HID + k] * dzb2[o];
-    }
-    const T g1 = T(1) - h1[k] * h1[k];
-    // dh1 = (1 - h1^2) dz1 contributes -2 h1 dz1 dhb to the adjoint of h1
-    hb += dhb * (T(-2) * h1[k] * dz1[k]);
-    out[4 * HID + k] = g1 * hb;
-    out[5 * HID + k] = g1 * dhb;
-  }
-  out[10 * HID] = alpha;
+  const T g1 = T(1) - h1 * h1;
+  // dh1 = (1 - h1^2) dz1 contributes -2 h1 dz1 dhb to the adjoint of h1
+  hb += dhb * (T(-2) * h1 * dz1);
+  out[4 * HID + l] = g1 * hb;
+  out[5 * HID + l] = g1 * dhb;
+  if (l == 0) out[10 * HID] = alpha;
 }
 
 template <class T> struct PairOf;
@@ -381,7 +387,7 @@ template <int P>
 void launch_wgrad(const WGradArgs<P>& a, hipStream_t stream) {
   using T = typename Types<P>::T;
   if (a.n > 0) {
-    const unsigned g = (unsigned)((a.n + 255) / 256 + a.n_el);
+    const unsigned g = (unsigned)((a.n + 256 / HID - 1) / (256 / HID) + a.n_el);
     hipLaunchKernelGGL(k_wgrad_atoms<P>, dim3(g), dim3(256), 0, stream, a);
   }
   hipLaunchKernelGGL(k_wgrad_chunks<T>, dim3((unsigned)a.nch, a.n_el), dim3(256), 0, stream, a.eoff, a.chunk, a.nch,
