@@ -383,19 +383,18 @@ __global__ void __launch_bounds__(256) k_neighbors(const double4* __restrict__ p
   if (tid == 0) cmax[X] = max(max(red[0], red[1]), max(red[2], red[3]));
 }
 
-// flags[2] = max over cells of cmax (one workgroup).
-__global__ void __launch_bounds__(1024) k_max_count(int ncells, const int* __restrict__ cmax, int* __restrict__ flags) {
-  __shared__ int red[16];
+// flags[2] = max over cells of cmax: each block takes 4096 cells, then one
+// atomic max per block (flags[2] is cleared before the neighbour build).
+constexpr int MAXC_PER = 4096;
+__global__ void __launch_bounds__(256) k_max_count(int ncells, const int* __restrict__ cmax, int* __restrict__ flags) {
+  __shared__ int red[4];
+  const int lo = blockIdx.x * MAXC_PER, hi = min(ncells, lo + MAXC_PER);
   int m = 0;
-  for (int i = threadIdx.x; i < ncells; i += 1024) m = max(m, cmax[i]);
+  for (int i = lo + threadIdx.x; i < hi; i += 256) m = max(m, cmax[i]);
   for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < 16; ++w) m = max(m, red[w]);
-    m = max(m, red[0]);
-    flags[2] = m;
-  }
+  if (threadIdx.x == 0) atomicMax(&flags[2], max(max(red[0], red[1]), max(red[2], red[3])));
 }
 
 // Work counts of one evaluation, one thread per centre:
@@ -496,7 +495,8 @@ void launch_neighbors(const BinArgs& a, double rc, int cap, typename Vec4<T>::ty
   if (a.n == 0) return;
   hipLaunchKernelGGL(k_neighbors<T>, dim3((unsigned)a.total_cells), dim3(256), 0, stream, a.pos4, a.st, a.n_struct,
                      a.start, a.n_el, a.total_cells, rc * rc, cap, nbr, nnb, a.flags, cmax);
-  hipLaunchKernelGGL(k_max_count, dim3(1), dim3(1024), 0, stream, a.total_cells, cmax, a.flags);
+  hipLaunchKernelGGL(k_max_count, dim3((unsigned)std::max(1, (a.total_cells + MAXC_PER - 1) / MAXC_PER)), dim3(256), 0,
+                     stream, a.total_cells, cmax, a.flags);
 }
 template void launch_neighbors<float>(const BinArgs&, double, int, float4*, int4*, int*, hipStream_t);
 template void launch_neighbors<double>(const BinArgs&, double, int, double4*, int4*, int*, hipStream_t);
