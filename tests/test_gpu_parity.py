@@ -261,3 +261,36 @@ def test_overlapping_call_on_one_handle_is_refused():
     assert e == e_fresh
     other.close()
     pot.close()
+
+
+def test_back_to_back_batches_on_a_side_stream(pots):
+    """Batch calls return with their last kernels still queued: two calls of
+    different batch layouts queued back to back on a non-default stream (default
+    priority), with no host wait between them, each equal the same call made
+    alone on the default stream (energies and E_i exactly; forces, which sum
+    through atomics, to 1e-12 of their scale)."""
+    import torch
+
+    pot = pots["fp64"]
+
+    def batch(boxes):
+        pos = torch.tensor(np.concatenate([b.pos for b in boxes]), dtype=torch.float64, device="cuda")
+        types = torch.tensor(np.concatenate([b.types for b in boxes]), dtype=torch.int32, device="cuda")
+        offs = np.cumsum([0] + [b.n_atoms for b in boxes])
+        return pos, types, offs, np.stack([b.box for b in boxes])
+
+    layouts = ([synth.water_box(4, 40), synth.water_box(5, 41)], [synth.water_box(6, 42)])
+    ins = [batch(bs) for bs in layouts]
+    ref = []
+    for x in ins:
+        out = pot.compute_batch(*x)
+        ref.append([t.cpu().numpy() for t in out])
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        outs = [pot.compute_batch(*x, stream=side) for x in ins]
+    side.synchronize()
+    for (eb, ei, f), (reb, rei, rf) in zip(outs, ref):
+        assert np.array_equal(eb.cpu().numpy(), reb)
+        assert np.array_equal(ei.cpu().numpy(), rei)
+        np.testing.assert_allclose(f.cpu().numpy(), rf, rtol=0, atol=1e-12 * np.sqrt(np.mean(rf ** 2)))
