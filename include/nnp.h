@@ -140,8 +140,11 @@ nnp_status nnp_create(int n_el, const char* const* elements, int n_sf, const nnp
  * Outputs are in the caller's atom order.  The neighbour list is rebuilt on
  * every call; if an atom has more neighbours than the current capacity the
  * handle grows it and recomputes (not an error).  Synchronises the stream.
- * Errors: NNP_E_ARG, NNP_E_BOX (checked before any launch), NNP_E_TYPE
- * (detected on the device; reported by the same call), NNP_E_HIP, NNP_E_NOMEM. */
+ * Positions may lie outside the box (they are wrapped) but must be finite.
+ * Errors: NNP_E_ARG, NNP_E_BOX (checked before any launch), NNP_E_TYPE and
+ * NNP_E_ARG for a NaN or infinite coordinate (both detected on the device by
+ * the binning pass and reported by the same call, before any SF or force
+ * kernel is launched), NNP_E_HIP, NNP_E_NOMEM. */
 nnp_status nnp_compute(nnp_handle* h, int64_t n_atoms, const void* pos, const int32_t* types,
                        const double box[3], double* energy, void* atom_energy, void* forces,
                        void* stream);
@@ -169,7 +172,14 @@ nnp_status nnp_compute_batch(nnp_handle* h, int n_struct, const int64_t* atom_of
  * nnp_compute_batch with the same arguments:
  *   dL/dtheta = sum_b dL/dE_b dE_b/dtheta + sum_m dL/dF_m . dF_m/dtheta.
  * By default the descriptor derivatives are recomputed, not stored (see
- * nnp_set_derivative_mode for the stored alternative).
+ * nnp_set_derivative_mode for the stored alternative).  Called with the
+ * inputs of the last nnp_compute_batch on this handle (same batch layout and
+ * boxes, checked on the host; positions and types bitwise equal, checked on
+ * the device, the host waiting for that one flag), it reuses that forward's
+ * sorted order, neighbour list and scaled SFs and runs only the
+ * force-adjoint product and the weight gradient; with other inputs it
+ * rebuilds them first.  Any other call on the handle in between (except
+ * nnp_set_params and the query functions) ends the reuse.
  *  dL_dE        device double [n_struct] (may be NULL: no energy term)
  *  dL_dF        device [n_atoms][3] in the positions' type (may be NULL: no force term)
  *  grad_params  device double [nnp_n_params(h)], overwritten; flat layout of
@@ -214,7 +224,14 @@ nnp_status nnp_md_run(nnp_handle* h, int64_t n_atoms, void* pos, void* vel, void
  *  NNP_PAR_THREAD  one thread per centre atom, walking its neighbours and
  *                  pairs alone (the paper's flat level); kept for comparison.
  *  NNP_PAR_AUTO    (default) the faster level; on this device that is a
- *                  wave per centre for long and short neighbour rows alike.
+ *                  wave per centre for long and short neighbour rows alike,
+ *                  except for a batch whose densest atom has more neighbours
+ *                  than the wave level can stage in LDS (160 KB per
+ *                  workgroup of four waves: from about 310 neighbours in
+ *                  the FP64 force-adjoint pass to about 730 in the FP32
+ *                  force pass): that batch takes the thread level.
+ * NNP_PAR_WAVE with such a batch is NNP_E_ARG, reported before any SF or
+ * force kernel is launched.
  * Both give the same results up to rounding order; the force-adjoint pass of
  * nnp_backward follows the same choice.  An unknown mode is NNP_E_ARG.
  */
@@ -236,6 +253,8 @@ nnp_status nnp_set_parallelism(nnp_handle* h, int mode);
  *                       inputs are the same is checked (batch layout on the
  *                       host, positions and types bitwise on the device);
  *                       otherwise nnp_backward recomputes the store first.
+ * A batch whose densest atom has more neighbours than the store's kernel can
+ * stage in LDS is computed with recomputed derivatives instead.
  * NNP_DERIV_STORED needs an NNP_FP64 or NNP_FP32 handle (NNP_E_STATE
  * otherwise); an unknown mode is NNP_E_ARG.  Takes effect at the next call.
  */

@@ -58,15 +58,16 @@ struct nnp_handle {
   std::vector<double> t_ms;
   std::vector<hipEvent_t> events;
   bool has_forward = false;
-  // stored-Jacobian differentiation form: the last forward's inputs, for
-  // reuse of its J store by nnp_backward
   int parallelism = NNP_PAR_AUTO;        // SF and force passes: wave or thread per centre
   bool has_wide = false;                 // the table holds wide angular SFs (thread-per-centre passes only)
   int deriv_mode = NNP_DERIV_RECOMPUTE;
-  bool jac_valid = false;
-  int jac_cap = 0;
-  std::vector<int64_t> jac_offs;
-  std::vector<double> jac_boxes;
+  // The last batch forward's inputs, for nnp_backward: while fwd_valid, the
+  // workspace holds that forward's sorted order, neighbour list and G~ (and
+  // its J store in the stored-Jacobian mode).
+  bool fwd_valid = false;
+  int fwd_cap = 0;
+  std::vector<int64_t> fwd_offs;
+  std::vector<double> fwd_boxes;
   std::atomic<int> busy{0};              // an ABI call is running on this handle
 };
 
@@ -405,7 +406,7 @@ nnp_status prepare(nnp_handle* h, Common& cm, const IO* pos, const int32_t* type
   if ((st = ensure_t(h, "eoff", MAX_EL + 1, &a.eoff))) return st;
   if ((st = ensure_t(h, "flags", 4, &a.flags))) return st;
   if (!sort) return NNP_OK;
-  h->jac_valid = false;  // the sorted order, neighbour list and J store are about to change
+  h->fwd_valid = false;  // the sorted order, neighbour list, G~ and J store are about to change
   launch_fill_int(a.flags, 4, 0, stream);
   launch_bin_sort<IO>(a, pos, stream);
   return NNP_OK;
@@ -464,8 +465,12 @@ int check_flags(nnp_handle* h, hipStream_t stream, Common& cm, nnp_status* st) {
     *st = fail(h, NNP_E_HIP, std::string("readback: ") + hipGetErrorString(e));
     return -1;
   }
-  if (h->h_flags[0]) {
+  if (h->h_flags[0] & 1) {
     *st = fail(h, NNP_E_TYPE, "atom type outside [0, n_el)");
+    return -1;
+  }
+  if (h->h_flags[0] & 2) {
+    *st = fail(h, NNP_E_ARG, "non-finite atom position (NaN or infinity)");
     return -1;
   }
   if (h->h_flags[1] > h->cap) {
@@ -478,14 +483,37 @@ int check_flags(nnp_handle* h, hipStream_t stream, Common& cm, nnp_status* st) {
   return 0;
 }
 
-// Thread per centre for the SF and force passes only when asked for: a wave
-// per centre was measured faster on both workloads, short rows included.
-bool flat_passes(const nnp_handle* h) { return h->parallelism == NNP_PAR_THREAD || h->has_wide; }
-
-// The stored-Jacobian form applies to the FP64 and FP32 handles.
+// Level of the pair passes of modes mode_a and mode_b (0 SF, 1 force, 2
+// force-adjoint product).  A thread per centre when asked for or when the
+// table holds wide angular SFs; otherwise a wave per centre (measured faster
+// on both workloads, short rows included), unless an atom has more
+// neighbours than the wave level can stage in LDS: then NNP_PAR_AUTO takes
+// the thread level, which reads the rows from HBM, and an explicit
+// NNP_PAR_WAVE is refused before any launch.
 template <int P>
-bool stored_jacobian(const nnp_handle* h) {
-  return P != P_BF16 && h->deriv_mode == NNP_DERIV_STORED;
+nnp_status use_flat(nnp_handle* h, int mode_a, int mode_b, bool* flat) {
+  *flat = h->parallelism == NNP_PAR_THREAD || h->has_wide;
+  if (*flat) return NNP_OK;
+  const size_t lds =
+      std::max(triplet_lds_bytes<P>(mode_a, h->variant, h->lcap), triplet_lds_bytes<P>(mode_b, h->variant, h->lcap));
+  if (lds <= lds_limit()) return NNP_OK;
+  if (h->parallelism == NNP_PAR_WAVE)
+    return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) + " neighbours needs " + std::to_string(lds) +
+                                  " bytes of LDS per workgroup at the wave level, more than the device allows");
+  *flat = true;
+  return NNP_OK;
+}
+
+// The stored-Jacobian form applies to the FP64 and FP32 handles, and to
+// batches whose densest atom its kernel can stage in LDS; otherwise the
+// call recomputes the derivatives.
+template <int P>
+bool use_store(const nnp_handle* h) {
+  if constexpr (P == P_BF16) {
+    return false;
+  } else {
+    return h->deriv_mode == NNP_DERIV_STORED && jac_lds_bytes<P>(h->lcap) <= lds_limit();
+  }
 }
 
 template <int P>
@@ -507,9 +535,10 @@ nnp_status jac_setup(nnp_handle* h, Common& cm, JacArgs<P>& j) {
   return ensure_t(h, "J", (size_t)3 * ns_max * j.plane, &j.J);
 }
 
-// Keeps a copy of the inputs whose J store is now in the workspace.
+// Keeps a copy of the inputs whose sorted order, neighbour list and G~ (and
+// J store) are now in the workspace.
 template <class IO>
-nnp_status jac_remember(nnp_handle* h, const Common& cm, const IO* pos, const int32_t* types, hipStream_t stream) {
+nnp_status fwd_remember(nnp_handle* h, const Common& cm, const IO* pos, const int32_t* types, hipStream_t stream) {
   const int64_t n = cm.B.n;
   IO* sp;
   int32_t* stp;
@@ -520,27 +549,28 @@ nnp_status jac_remember(nnp_handle* h, const Common& cm, const IO* pos, const in
     NNP_HIP(h, hipMemcpyAsync(sp, pos, (size_t)n * 3 * sizeof(IO), hipMemcpyDeviceToDevice, stream));
     NNP_HIP(h, hipMemcpyAsync(stp, types, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
   }
-  h->jac_offs.assign(cm.B.soff.begin(), cm.B.soff.end());
-  h->jac_boxes.clear();
-  for (const auto& d : cm.B.st) h->jac_boxes.insert(h->jac_boxes.end(), d.L, d.L + 3);
-  h->jac_cap = h->cap;
+  h->fwd_offs.assign(cm.B.soff.begin(), cm.B.soff.end());
+  h->fwd_boxes.clear();
+  for (const auto& d : cm.B.st) h->fwd_boxes.insert(h->fwd_boxes.end(), d.L, d.L + 3);
+  h->fwd_cap = h->cap;
   return NNP_OK;
 }
 
-// True if the workspace still holds the J store of exactly these inputs
-// (same batch layout, same capacity, bitwise equal positions and types).
-// Binds the sorted-order buffers of cm either way.
+// True if the workspace still holds the forward results of exactly these
+// inputs (same batch layout, same capacity, bitwise equal positions and
+// types, compared on the device; the host waits for that one flag).  Binds
+// the sorted-order buffers of cm either way.
 template <class IO>
-bool jac_reusable(nnp_handle* h, Common& cm, const IO* pos, const int32_t* types, hipStream_t stream,
+bool fwd_reusable(nnp_handle* h, Common& cm, const IO* pos, const int32_t* types, hipStream_t stream,
                   nnp_status* st) {
   *st = NNP_OK;
-  if (!h->jac_valid || h->jac_cap != h->cap) return false;
-  if (h->jac_offs.size() != cm.B.soff.size() ||
-      !std::equal(h->jac_offs.begin(), h->jac_offs.end(), cm.B.soff.begin()))
+  if (!h->fwd_valid || h->fwd_cap != h->cap) return false;
+  if (h->fwd_offs.size() != cm.B.soff.size() ||
+      !std::equal(h->fwd_offs.begin(), h->fwd_offs.end(), cm.B.soff.begin()))
     return false;
   std::vector<double> boxes;
   for (const auto& d : cm.B.st) boxes.insert(boxes.end(), d.L, d.L + 3);
-  if (boxes != h->jac_boxes) return false;
+  if (boxes != h->fwd_boxes) return false;
   IO* sp;
   int32_t* stp;
   if ((*st = ensure_t(h, "jpos", (size_t)std::max<int64_t>(cm.B.n, 1) * 3, &sp))) return false;
@@ -560,7 +590,7 @@ bool jac_reusable(nnp_handle* h, Common& cm, const IO* pos, const int32_t* types
 template <int P>
 nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void* pos_v, const int32_t* types,
                    const double* boxes, double* energies_dev, double* energy_host, void* ei_v, void* f_v,
-                   hipStream_t stream) {
+                   hipStream_t stream, bool remember = false) {
   using T = typename Types<P>::T;
   using IO = typename Types<P>::IO;
   using FAcc = typename Types<P>::FAcc;
@@ -586,7 +616,6 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
   if ((st = ensure_t(h, "Ei_o", n1, &Ei_o))) return st;
   if ((st = ensure_t(h, "partial", std::max<size_t>(cm.B.chunk_lo.size(), 1), &partial))) return st;
   if ((st = ensure_t(h, "energies", n_struct, &energies))) return st;
-  const bool stored = stored_jacobian<P>(h);
   for (int attempt = 0; attempt < 8; ++attempt) {
     if ((st = build_neighbors<T>(h, cm, stream))) return st;
     const int r = check_flags(h, stream, cm, &st);
@@ -604,13 +633,11 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
     ma.Ei = Ei_s;
     ma.nets = reinterpret_cast<const T*>(h->d_nets);
     ma.tab = ta.tab;
+    const bool store = use_store<P>(h);
     if constexpr (P != P_BF16) {
-      if (stored) {
+      if (store) {
         JacArgs<P> ja;
         if ((st = jac_setup<P>(h, cm, ja))) return st;
-        if (jac_lds_bytes<P>(h->lcap) > lds_limit())
-          return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) +
-                                        " neighbours needs more LDS per workgroup than the device allows");
         ja.G = G;
         launch_jac<P>(ja, stream);
         mk.mark("sf");
@@ -621,16 +648,11 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
         ja.F = F_s;
         launch_jac_force<P>(ja, stream);
         mk.mark("force");
-        if ((st = jac_remember<IO>(h, cm, pos, types, stream))) return st;
       }
     }
-    if (!stored) {
-      const bool flat = flat_passes(h);
-      const size_t lds =
-          std::max(triplet_lds_bytes<P>(0, h->variant, h->lcap), triplet_lds_bytes<P>(1, h->variant, h->lcap));
-      if (!flat && lds > lds_limit())
-        return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) + " neighbours needs " +
-                                      std::to_string(lds) + " bytes of LDS per workgroup, more than the device allows");
+    if (!store) {
+      bool flat = false;
+      if ((st = use_flat<P>(h, 0, 1, &flat))) return st;
       ta.G = G;
       if (flat) launch_flat<P>(0, ta, stream);
       else launch_triplet<P>(0, h->variant, ta, stream);
@@ -644,6 +666,8 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
       else launch_triplet<P>(1, h->variant, ta, stream);
       mk.mark("force");
     }
+    const bool keep = remember || store;
+    if (keep && (st = fwd_remember<IO>(h, cm, pos, types, stream))) return st;
     launch_unpermute<IO, FAcc>(n, cm.bin.perm, Ei_s, F_s, Ei_o, reinterpret_cast<IO*>(ei_v),
                                reinterpret_cast<IO*>(f_v), stream);
     launch_energy(Ei_o, cm.d_clo, cm.d_chi, (int)cm.B.chunk_lo.size(), cm.d_sc, n_struct, partial, energies, stream);
@@ -659,7 +683,7 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
     if (energy_host) *energy_host = *h->h_energy;
     mk.finish();
     h->has_forward = true;
-    h->jac_valid = stored;
+    h->fwd_valid = keep;
     return NNP_OK;
   }
   return fail(h, NNP_E_STATE, "neighbour capacity did not converge");
@@ -696,15 +720,15 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
   if ((st = ensure_t(h, "wvec", (size_t)n1 * 11 * HID, &vec))) return st;
   if ((st = ensure_t(h, "wpart", (size_t)h->n_el * nch * NET_STRIDE, &part))) return st;
   if ((st = ensure_t(h, "wpad", (size_t)h->n_el * NET_STRIDE, &padded))) return st;
-  const bool stored = stored_jacobian<P>(h);
-  bool ready = false;  // G and the J store (or the neighbour list) describe these inputs
-  if (stored) {
-    ready = jac_reusable<IO>(h, cm, pos, types, stream, &st);
-    if (st) return st;
-    if (ready && (st = bind_neighbors<T>(h, cm))) return st;
-    mk.mark(ready ? "reuse" : "compare");
-  }
-  if (!ready) {
+  // With the inputs of the last batch forward, its sorted order, neighbour
+  // list and G~ (and J store) are reused: only the force-adjoint product and
+  // the weight gradient run.  Otherwise they are rebuilt first.
+  bool ready = fwd_reusable<IO>(h, cm, pos, types, stream, &st);
+  if (st) return st;
+  if (ready) {
+    if ((st = bind_neighbors<T>(h, cm))) return st;
+    mk.mark("reuse");
+  } else {
     if ((st = prepare<IO>(h, cm, pos, types, stream))) return st;
     mk.mark("bin_sort");
   }
@@ -714,38 +738,35 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
     if (r < 0) return st;
     if (r > 0) continue;  // capacity grew: rebuild the neighbour list
     mk.mark("neighbors");
+    const bool store = use_store<P>(h);
     if constexpr (P != P_BF16) {
-      if (stored) {
+      if (store) {
         JacArgs<P> ja;
         if ((st = jac_setup<P>(h, cm, ja))) return st;
-        if (jac_lds_bytes<P>(h->lcap) > lds_limit())
-          return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) +
-                                        " neighbours needs more LDS per workgroup than the device allows");
         ja.G = G;
         launch_jac<P>(ja, stream);
-        if ((st = jac_remember<IO>(h, cm, pos, types, stream))) return st;
         mk.mark("sf");
       }
     }
-    if (!stored) {
+    if (!store) {
       TripArgs<P> ta = trip_args<P>(h, cm);
-      if (!flat_passes(h) &&
-          std::max(triplet_lds_bytes<P>(0, h->variant, h->lcap), triplet_lds_bytes<P>(2, h->variant, h->lcap)) >
-              lds_limit())
-        return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) +
-                                      " neighbours needs more LDS per workgroup than the device allows");
+      bool flat = false;
+      if ((st = use_flat<P>(h, 0, 0, &flat))) return st;
       ta.G = G;
-      if (flat_passes(h)) launch_flat<P>(0, ta, stream);
+      if (flat) launch_flat<P>(0, ta, stream);
       else launch_triplet<P>(0, h->variant, ta, stream);
       mk.mark("sf");
     }
+    if ((st = fwd_remember<IO>(h, cm, pos, types, stream))) return st;
+    h->fwd_valid = true;
     ready = true;
   }
   if (!ready) return fail(h, NNP_E_STATE, "neighbour capacity did not converge");
   if (dLdF) launch_permute_rows3<IO>(n, cm.bin.perm, dLdF, delta, stream);
   else launch_fill<IO>(delta, n * 3, IO(0), stream);
+  const bool store = use_store<P>(h);
   if constexpr (P != P_BF16) {
-    if (stored) {
+    if (store) {
       JacArgs<P> ja;
       if ((st = jac_setup<P>(h, cm, ja))) return st;
       ja.delta = delta;
@@ -753,11 +774,13 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
       launch_jac_jvp<P>(ja, stream);
     }
   }
-  if (!stored) {
+  if (!store) {
     TripArgs<P> ta = trip_args<P>(h, cm);
+    bool flat = false;
+    if ((st = use_flat<P>(h, 2, 2, &flat))) return st;
     ta.delta = delta;
     ta.V = V;
-    if (flat_passes(h)) launch_flat<P>(2, ta, stream);
+    if (flat) launch_flat<P>(2, ta, stream);
     else launch_triplet<P>(2, h->variant, ta, stream);
   }
   mk.mark("jvp");
@@ -786,7 +809,6 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
   // the gradient is ready in stream order; the host waits only for profiling
   if (h->prof) NNP_HIP(h, hipStreamSynchronize(stream));
   mk.finish();
-  h->jac_valid = stored;
   return NNP_OK;
 }
 
@@ -1070,9 +1092,9 @@ nnp_status nnp_compute_batch(nnp_handle* h, int n_struct, const int64_t* atom_of
   if (!claim.ok) return NNP_E_STATE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   switch (h->prec) {
-    case NNP_FP64: return forward<P_FP64>(h, n_struct, atom_offsets, pos, types, boxes, energies, nullptr, atom_energy, forces, s);
-    case NNP_FP32: return forward<P_FP32>(h, n_struct, atom_offsets, pos, types, boxes, energies, nullptr, atom_energy, forces, s);
-    default: return forward<P_BF16>(h, n_struct, atom_offsets, pos, types, boxes, energies, nullptr, atom_energy, forces, s);
+    case NNP_FP64: return forward<P_FP64>(h, n_struct, atom_offsets, pos, types, boxes, energies, nullptr, atom_energy, forces, s, true);
+    case NNP_FP32: return forward<P_FP32>(h, n_struct, atom_offsets, pos, types, boxes, energies, nullptr, atom_energy, forces, s, true);
+    default: return forward<P_BF16>(h, n_struct, atom_offsets, pos, types, boxes, energies, nullptr, atom_energy, forces, s, true);
   }
 }
 
@@ -1198,7 +1220,7 @@ nnp_status nnp_set_derivative_mode(nnp_handle* h, int mode) {
     return fail(h, NNP_E_ARG, "derivative mode must be NNP_DERIV_RECOMPUTE or NNP_DERIV_STORED");
   if (mode == NNP_DERIV_STORED && h->prec == NNP_BF16_MIXED)
     return fail(h, NNP_E_STATE, "the stored-Jacobian mode needs an NNP_FP64 or NNP_FP32 handle");
-  if (mode != h->deriv_mode) h->jac_valid = false;
+  if (mode != h->deriv_mode) h->fwd_valid = false;
   h->deriv_mode = mode;
   return NNP_OK;
 }
@@ -1221,7 +1243,7 @@ nnp_status nnp_set_neighbor_capacity(nnp_handle* h, int cap) {
   if (cap < 8) return fail(h, NNP_E_ARG, "capacity must be >= 8");
   h->cap_override = cap;
   h->cap = cap;
-  h->jac_valid = false;
+  h->fwd_valid = false;
   return NNP_OK;
 }
 

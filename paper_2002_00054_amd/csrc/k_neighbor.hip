@@ -49,11 +49,15 @@ __global__ void __launch_bounds__(256) k_bin(int64_t n, const TIn* __restrict__ 
     e = 0;  // keep every index in range; the call reports the error
   }
   int c[3];
+  bool finite = true;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double w = wrap_coord((double)pos[3 * i + a], S.L[a], S.invL[a]);
+    const double x = (double)pos[3 * i + a];
+    finite = finite && isfinite(x);
+    const double w = wrap_coord(x, S.L[a], S.invL[a]);
     c[a] = cell_coord(w, S.invL[a], S.ncell[a]);
   }
+  if (!finite) atomicOr(&flags[0], 2);  // the call reports NNP_E_ARG
   const int k = e * total_cells + S.cellbase + (c[0] * S.ncell[1] + c[1]) * S.ncell[2] + c[2];
   key[i] = k;
   atomicAdd(&count[k], 1);

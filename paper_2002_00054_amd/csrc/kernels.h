@@ -23,7 +23,7 @@ struct BinArgs {
   int* perm_raw;             // [n] the scatter's order within each bin, before the bin sort
   double4* pos4;             // [n] sorted wrapped positions + ids
   int* eoff;                 // [n_el + 1] element offsets of the sorted order
-  int* flags;                // [0] bad type, [1] max neighbour count beyond cap, [2] max count
+  int* flags;                // [0] bit 0 bad type, bit 1 non-finite position, [1] max neighbour count beyond cap, [2] max count
 };
 
 void launch_fill_int(int* p, int64_t n, int v, hipStream_t stream);

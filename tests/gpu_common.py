@@ -60,3 +60,40 @@ def check_fp32(ei, f, ref_ei, ref_f, tol_e=1e-5, tol_f=1e-4):
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+def gpu_loss_and_grad(pot, boxes, Ehat, Fhat, params):
+    """Energy+force loss of a batch (per-atom energy MSE + 0.1 force MSE)
+    and its parameter gradient, through the autograd function over
+    nnp_compute_batch / nnp_backward."""
+    import torch
+
+    from paper_2002_00054_amd.nnp import energy_forces
+
+    dt = pot.dtype
+    pos = torch.tensor(np.concatenate([b.pos for b in boxes]), dtype=dt, device="cuda")
+    types = torch.tensor(np.concatenate([b.types for b in boxes]), dtype=torch.int32, device="cuda")
+    offs = np.cumsum([0] + [b.n_atoms for b in boxes])
+    bx = np.stack([b.box for b in boxes])
+    th = torch.tensor(params, dtype=torch.float64, device="cuda", requires_grad=True)
+    E, F = energy_forces(th, pos, pot, types, offs, bx)
+    N = torch.tensor([b.n_atoms for b in boxes], dtype=torch.float64, device="cuda")
+    Eh = torch.tensor(Ehat, dtype=torch.float64, device="cuda")
+    Fh = torch.tensor(Fhat, dtype=dt, device="cuda")
+    L = torch.mean(((E - Eh) / N) ** 2) + 0.1 * torch.sum((F - Fh).double() ** 2) / (3 * N.sum())
+    (g,) = torch.autograd.grad(L, th)
+    return L.item(), g.cpu().numpy()
+
+
+def per_tensor_rel(g, ref, nets):
+    """Relative L2 error of each parameter tensor (W1, b1, W2, b2, w3, b3 per
+    element, in the flat parameter order)."""
+    out = []
+    o = 0
+    for n in nets:
+        for w, b in zip(n.W, n.b):
+            for sz in (w.size, b.size):
+                a, r = g[o:o + sz], ref[o:o + sz]
+                out.append(np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-300))
+                o += sz
+    return np.array(out)

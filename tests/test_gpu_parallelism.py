@@ -7,8 +7,9 @@ import numpy as np
 import pytest
 
 import oracle
-from common import oracle_water
-from gpu_common import check_fp32, check_fp64, make_potential, oracle_input, run, say
+from common import oracle_water, water_potential
+from gpu_common import (check_fp32, check_fp64, gpu_loss_and_grad, make_potential, oracle_input,
+                        per_tensor_rel, run, say)
 from paper_2002_00054_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -87,9 +88,10 @@ def _dense_ball():
 def test_dense_cluster_beyond_wave_lds():
     """Atoms with more neighbours than the wave level can stage in LDS (about
     580 per atom: over 190 KB per workgroup in FP64, above the 160 KB a
-    workgroup can have) are refused by the wave level with NNP_E_ARG before
-    any launch; on the same handle the thread level, which reads the rows
-    from HBM, computes them, against the oracle (FP64)."""
+    workgroup can have).  Under the default level the handle takes the
+    thread level, which reads the rows from HBM, and matches the oracle
+    (FP64), forward and weight gradient alike; an explicit request for the
+    wave level is refused with NNP_E_ARG before any launch."""
     from paper_2002_00054_amd.nnp import NNPError
 
     b = _dense_ball()
@@ -97,12 +99,30 @@ def test_dense_cluster_beyond_wave_lds():
     d2 = np.sum((b.pos[:, None, :] - b.pos[None, :, :]) ** 2, axis=-1)
     assert np.max(d2) < synth.RCUT ** 2
     say("dense ball", b.n_atoms)
-    pot = make_potential("fp64")
-    with pytest.raises(NNPError, match="NNP_E_ARG.*LDS"):
-        run(pot, b)
-    pot.set_parallelism("thread")
-    e, ei, f = run(pot, b)
     ref = oracle_water().compute(b.pos, b.types, b.box, use_cells=True)
+    pot = make_potential("fp64")
+    e, ei, f = run(pot, b)
     check_fp64(ei, f, ref["Ei"], ref["F"])
     assert e == pytest.approx(float(np.sum(ref["Ei"])), rel=1e-10)
+    pot.set_parallelism("wave")
+    with pytest.raises(NNPError, match="NNP_E_ARG.*LDS"):
+        run(pot, b)
+    pot.close()
+
+
+def test_dense_cluster_gradient_default_level():
+    """The weight gradient of the dense ball under the default level (its
+    force-adjoint pass also falls back to the thread level) against the
+    oracle, FP64, 1e-8 per parameter tensor."""
+    b = _dense_ball()
+    table, nets = water_potential()
+    teacher = synth.teacher_nets()
+    Ehat, Fhat = oracle.batch_energy_forces(oracle.Potential(table, teacher), [b])
+    L_ref, g_ref = oracle.loss_and_grad(oracle.Potential(table, nets), [b], Ehat, Fhat)
+    pot = make_potential("fp64")
+    L, g = gpu_loss_and_grad(pot, [b], Ehat, Fhat, synth.flat_params(nets))
+    per = per_tensor_rel(g, g_ref, nets)
+    say("dense ball gradient per-tensor rel-L2 max", float(per.max()))
+    assert L == pytest.approx(L_ref, rel=1e-10)
+    assert per.max() < 1e-8, per
     pot.close()

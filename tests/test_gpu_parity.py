@@ -137,6 +137,17 @@ def test_errors_are_reported(pots):
     bad[5] = -1
     with pytest.raises(NNPError, match="NNP_E_TYPE"):
         pot.compute(pos, bad, b.box)
+    # a non-finite coordinate is reported, in both forms and in the batch call
+    for prec in ("fp64", "fp32"):
+        p = pots[prec]
+        pos_p, _ = to_dev(b, p.dtype)
+        for v in (float("nan"), float("inf"), float("-inf")):
+            badpos = pos_p.clone()
+            badpos[17, 1] = v
+            with pytest.raises(NNPError, match="NNP_E_ARG.*non-finite"):
+                p.compute(badpos, types, b.box)
+            with pytest.raises(NNPError, match="NNP_E_ARG.*non-finite"):
+                p.compute_batch(badpos, types, [0, b.n_atoms], b.box[None])
     # the handle still works afterwards
     e, ei, f = run(pot, b)
     assert np.isfinite(e)
