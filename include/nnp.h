@@ -40,6 +40,7 @@
 #ifndef NNP_H
 #define NNP_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -148,6 +149,32 @@ nnp_status nnp_create(int n_el, const char* const* elements, int n_sf, const nnp
 nnp_status nnp_compute(nnp_handle* h, int64_t n_atoms, const void* pos, const int32_t* types,
                        const double box[3], double* energy, void* atom_energy, void* forces,
                        void* stream);
+
+/*
+ * nnp_compute without any allocation, for callers that cannot allocate device
+ * memory during the call (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments, outputs, errors and
+ * synchronisation are those of nnp_compute; the derivatives are always
+ * recomputed (the stored-Jacobian mode does not apply) and profiling is off
+ * for the call.
+ * Every intermediate buffer is carved from one static device array of
+ * NNP_NOALLOC_SCRATCH_BYTES bytes that the library holds on each device it
+ * runs on until the process ends, shared by every handle on that device; the
+ * call makes no hipMalloc, hipFree or other allocating call (the pinned host
+ * staging it needs is allocated by nnp_create).  The array keeps the last
+ * call's contents; every value a call reads is written or cleared by that
+ * call first.  Calls that overlap on one device (two streams, two host
+ * threads, two handles) race on the array: serialise them.
+ *  n_atoms  at most NNP_NOALLOC_MAX_ATOMS, else NNP_E_ARG before any launch.
+ * A structure whose buffers (about 5 KB per atom in FP64 and 2.5 KB in FP32
+ * at the water density's 128 neighbour slots) exceed the array returns
+ * NNP_E_NOMEM; the handle's device must be the current device (else
+ * NNP_E_STATE).  The handle's own workspace is left untouched. */
+#define NNP_NOALLOC_MAX_ATOMS 16384
+#define NNP_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+nnp_status nnp_compute_noalloc(nnp_handle* h, int64_t n_atoms, const void* pos, const int32_t* types,
+                               const double box[3], double* energy, void* atom_energy, void* forces,
+                               void* stream);
 
 /*
  * The same for a batch of independent structures stored back to back.

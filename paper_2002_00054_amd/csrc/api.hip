@@ -7,16 +7,43 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/nnp.h"
 #include "kernels.h"
 
+// Workspace of nnp_compute_noalloc: a static array, one copy per device,
+// kept until the process ends.  Host code never passes this name to a kernel
+// or a copy (on the host it stands for the device symbol, not an address):
+// the device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[NNP_NOALLOC_SCRATCH_BYTES];
+
 namespace nnp {
 namespace {
 
 thread_local std::string g_create_error;
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[MAX_DEVICES] = {};  // device address of `scratch`, per device
+
+// Device address of the static workspace on device dev (the current device),
+// looked up on the first call for that device.
+hipError_t scratch_address(int dev, unsigned char** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 struct DevBuf {
   void* p = nullptr;
@@ -69,6 +96,13 @@ struct nnp_handle {
   std::vector<int64_t> fwd_offs;
   std::vector<double> fwd_boxes;
   std::atomic<int> busy{0};              // an ABI call is running on this handle
+  // nnp_compute_noalloc: while arena_on, named buffers are carved from the
+  // device's static workspace (bump order, reset at every such call) instead
+  // of the handle's own allocations, and nothing is allocated.
+  unsigned char* scratch = nullptr;      // this device's copy of the static workspace
+  bool arena_on = false;
+  size_t arena_used = 0;
+  std::map<std::string, nnp::DevBuf> arena_bufs;
 };
 
 namespace nnp {
@@ -132,8 +166,29 @@ size_t lds_limit() {
   return (size_t)v;
 }
 
+// Named buffer of the static workspace (no allocation): reused while large
+// enough, grown in place if it is the last one carved, else carved anew.
+nnp_status ensure_arena(nnp_handle* h, const char* name, size_t bytes, void** out) {
+  DevBuf& b = h->arena_bufs[name];
+  if (b.bytes < bytes) {
+    const size_t nb = (std::max<size_t>(bytes, 256) + 255) & ~(size_t)255;
+    const bool last = b.p && static_cast<unsigned char*>(b.p) + b.bytes == h->scratch + h->arena_used;
+    const size_t start = last ? (size_t)(static_cast<unsigned char*>(b.p) - h->scratch) : h->arena_used;
+    if (start + nb > (size_t)NNP_NOALLOC_SCRATCH_BYTES)
+      return fail(h, NNP_E_NOMEM, std::string("the call needs more than the ") +
+                                      std::to_string((long long)NNP_NOALLOC_SCRATCH_BYTES) +
+                                      " bytes of the static workspace (buffer " + name + ")");
+    b.p = h->scratch + start;
+    b.bytes = nb;
+    h->arena_used = start + nb;
+  }
+  *out = b.p;
+  return NNP_OK;
+}
+
 // Grow-only named device buffer.
 nnp_status ensure(nnp_handle* h, const char* name, size_t bytes, void** out) {
+  if (h->arena_on) return ensure_arena(h, name, bytes, out);
   DevBuf& b = h->ws[name];
   if (b.bytes < bytes) {
     if (b.p) {
@@ -167,6 +222,7 @@ nnp_status ensure_t(nnp_handle* h, const char* name, size_t count, X** out) {
 
 nnp_status stage(nnp_handle* h, size_t bytes) {
   if (h->h_stage_bytes >= bytes) return NNP_OK;
+  if (h->arena_on) return fail(h, NNP_E_NOMEM, "the batch description exceeds the pinned staging block");
   if (h->h_stage) (void)hipHostFree(h->h_stage);
   h->h_stage = nullptr;
   h->h_stage_bytes = 0;
@@ -512,7 +568,7 @@ bool use_store(const nnp_handle* h) {
   if constexpr (P == P_BF16) {
     return false;
   } else {
-    return h->deriv_mode == NNP_DERIV_STORED && jac_lds_bytes<P>(h->lcap) <= lds_limit();
+    return h->deriv_mode == NNP_DERIV_STORED && !h->arena_on && jac_lds_bytes<P>(h->lcap) <= lds_limit();
   }
 }
 
@@ -1015,6 +1071,10 @@ nnp_status nnp_create(int n_el, const char* const* elements, int n_sf, const nnp
     return s;
   };
   if (hipGetDevice(&h->device) != hipSuccess) return bail(fail(h, NNP_E_HIP, "hipGetDevice failed"));
+  {
+    const hipError_t e = scratch_address(h->device, &h->scratch);
+    if (e != hipSuccess) return bail(fail(h, NNP_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)));
+  }
   if (prec == NNP_FP64) {
     if (hipMalloc(&h->d_tab, sizeof(DevTab<double>)) != hipSuccess) return bail(fail(h, NNP_E_NOMEM, "table alloc"));
     if (hipMemcpy(h->d_tab, &h->tab_d, sizeof(DevTab<double>), hipMemcpyHostToDevice) != hipSuccess)
@@ -1034,6 +1094,7 @@ nnp_status nnp_create(int n_el, const char* const* elements, int n_sf, const nnp
     return bail(fail(h, NNP_E_NOMEM, "pinned flags"));
   if (hipHostMalloc((void**)&h->h_energy, sizeof(double), hipHostMallocDefault) != hipSuccess)
     return bail(fail(h, NNP_E_NOMEM, "pinned energy"));
+  if ((st = stage(h, 4096))) return bail(st);  // staging of one structure's batch description
   *out = h;
   return NNP_OK;
 }
@@ -1114,6 +1175,40 @@ nnp_status nnp_compute(nnp_handle* h, int64_t n_atoms, const void* pos, const in
     case NNP_FP32: st = forward<P_FP32>(h, 1, offs, pos, types, box, nullptr, &e, atom_energy, forces, s); break;
     default: st = forward<P_BF16>(h, 1, offs, pos, types, box, nullptr, &e, atom_energy, forces, s); break;
   }
+  if (st == NNP_OK && energy) *energy = e;
+  return st;
+}
+
+nnp_status nnp_compute_noalloc(nnp_handle* h, int64_t n_atoms, const void* pos, const int32_t* types,
+                               const double box[3], double* energy, void* atom_energy, void* forces, void* stream) {
+  if (!h) return NNP_E_ARG;
+  Claim claim(h);
+  if (!claim.ok) return NNP_E_STATE;
+  if (n_atoms < 0 || n_atoms > NNP_NOALLOC_MAX_ATOMS)
+    return fail(h, NNP_E_ARG, "n_atoms must be in [0, " + std::to_string(NNP_NOALLOC_MAX_ATOMS) + "]");
+  if (!box) return fail(h, NNP_E_ARG, "box must not be NULL");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != h->device)
+    return fail(h, NNP_E_STATE, "the handle's device must be the current device");
+  const int64_t offs[2] = {0, n_atoms};
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // Every named buffer of the call is carved from this device's static
+  // workspace; profiling (which creates events) is off for the call.
+  h->arena_on = true;
+  h->arena_used = 0;
+  h->arena_bufs.clear();
+  const bool prof = h->prof;
+  h->prof = false;
+  double e = 0.0;
+  nnp_status st;
+  switch (h->prec) {
+    case NNP_FP64: st = forward<P_FP64>(h, 1, offs, pos, types, box, nullptr, &e, atom_energy, forces, s); break;
+    case NNP_FP32: st = forward<P_FP32>(h, 1, offs, pos, types, box, nullptr, &e, atom_energy, forces, s); break;
+    default: st = forward<P_BF16>(h, 1, offs, pos, types, box, nullptr, &e, atom_energy, forces, s); break;
+  }
+  h->prof = prof;
+  h->arena_on = false;
+  h->arena_bufs.clear();
   if (st == NNP_OK && energy) *energy = e;
   return st;
 }

@@ -21,7 +21,8 @@ STATUS = {0: "NNP_OK", -1: "NNP_E_ARG", -2: "NNP_E_BOX", -3: "NNP_E_TYPE", -4: "
           -5: "NNP_E_NOMEM", -6: "NNP_E_STATE"}
 
 #: Every symbol include/nnp.h declares.
-EXPORTS = ("nnp_create", "nnp_compute", "nnp_compute_batch", "nnp_backward", "nnp_n_params", "nnp_set_params",
+EXPORTS = ("nnp_create", "nnp_compute", "nnp_compute_noalloc", "nnp_compute_batch", "nnp_backward", "nnp_n_params",
+           "nnp_set_params",
            "nnp_get_params", "nnp_set_profiling", "nnp_last_timings", "nnp_neighbor_capacity",
            "nnp_set_neighbor_capacity", "nnp_count_work", "nnp_md_run", "nnp_set_parallelism",
            "nnp_set_derivative_mode",
@@ -68,6 +69,7 @@ def load_library(path: str = LIB_PATH):
     L.nnp_create.argtypes = [C.c_int, C.POINTER(C.c_char_p), C.c_int, C.POINTER(_SF), C.POINTER(_Net), C.c_int,
                              C.POINTER(vp)]
     L.nnp_compute.argtypes = [vp, i64, vp, vp, dp, dp, vp, vp, vp]
+    L.nnp_compute_noalloc.argtypes = [vp, i64, vp, vp, dp, dp, vp, vp, vp]
     L.nnp_compute_batch.argtypes = [vp, C.c_int, C.POINTER(i64), vp, vp, dp, vp, vp, vp, vp]
     L.nnp_backward.argtypes = [vp, C.c_int, C.POINTER(i64), vp, vp, dp, vp, vp, vp, vp]
     L.nnp_n_params.argtypes = [vp]
@@ -88,7 +90,8 @@ def load_library(path: str = LIB_PATH):
     L.nnp_destroy.restype = None
     L.nnp_last_error.argtypes = [vp]
     L.nnp_last_error.restype = C.c_char_p
-    for name in ("nnp_create", "nnp_compute", "nnp_compute_batch", "nnp_backward", "nnp_set_params",
+    for name in ("nnp_create", "nnp_compute", "nnp_compute_noalloc", "nnp_compute_batch", "nnp_backward",
+                 "nnp_set_params",
                  "nnp_get_params", "nnp_set_profiling", "nnp_set_neighbor_capacity", "nnp_last_timings",
                  "nnp_neighbor_capacity", "nnp_count_work", "nnp_md_run", "nnp_set_parallelism",
                  "nnp_set_derivative_mode"):
@@ -218,6 +221,20 @@ class Potential:
         self._check(self._L.nnp_compute(self._h, n, _ptr(pos), _ptr(types), boxa, C.byref(e), _ptr(ei), _ptr(f),
                                         _stream_ptr(stream)))
         return e.value, ei, f
+
+    def compute_noalloc(self, pos, types, box, ei, f, stream=None):
+        """nnp_compute into caller-allocated E_i [n] and F [n, 3] (either may be
+        None), with every intermediate buffer in the library's static device
+        workspace; returns E."""
+        pos, types = self._prep(pos, types)
+        for t in (ei, f):
+            if t is not None and (t.dtype != self.dtype or not t.is_cuda or not t.is_contiguous()):
+                raise TypeError("outputs must be contiguous device tensors of the positions' type")
+        boxa = (C.c_double * 3)(*[float(x) for x in box])
+        e = C.c_double(0.0)
+        self._check(self._L.nnp_compute_noalloc(self._h, pos.shape[0], _ptr(pos), _ptr(types), boxa, C.byref(e),
+                                                _ptr(ei), _ptr(f), _stream_ptr(stream)))
+        return e.value
 
     def compute_batch(self, pos, types, offsets, boxes, stream=None):
         """(E_b [B] float64 device tensor, E_i, F) of a batch of structures."""
