@@ -236,24 +236,30 @@ def report(table, nets, sections=None):
         del x, t
         torch.cuda.empty_cache()
     # MD driver: velocity Verlet steps of the 2M box (FP32) and of a 12,288-atom box (FP64)
-    for side, seed, form, dt, steps in (((88, 22, "fp32", 0.5, 30), (16, 12, "fp64", 0.25, 200)) if want("md") else ()):
+    md_cases = ((88, 22, "fp32", 0.5, 30), (16, 12, "fp64", 0.25, 200)) if want("md") else ()
+    for side, seed, form, dt, steps in md_cases:
         bb = synth.water_box(side, seed)
         pot = Potential(table, nets, precision=form)
-        x = torch.tensor(bb.pos, dtype=pot.dtype, device=dev)
-        v = torch.tensor(synth.thermal_velocities(bb.types, seed=seed), dtype=pot.dtype, device=dev)
         t = torch.tensor(bb.types, dtype=torch.int32, device=dev)
-        pot.md_run(x, v, t, bb.box, synth.WATER_MASSES, dt, 1)  # warm-up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, ep, ek = pot.md_run(x, v, t, bb.box, synth.WATER_MASSES, dt, steps)
-        el = time.perf_counter() - t0
-        et = ep + ek
-        print(json.dumps({"report": "md", "form": form, "atoms": bb.n_atoms, "dt_fs": dt, "steps": steps,
-                          "ms_per_step": 1e3 * el / steps, "atom_steps_per_s": bb.n_atoms * steps / el,
-                          "max_abs_dE_total_per_atom": float(np.max(np.abs(et - et[0]))) / bb.n_atoms,
-                          "ekin_start": float(ek[0]), "ekin_end": float(ek[-1])}), flush=True)
+        v_init = synth.thermal_velocities(bb.types, seed=seed)
+        for skin in (0.0, 0.5, 1.0, 2.0):  # 0: neighbour list rebuilt at every step
+            pot.set_md_skin(skin)
+            x = torch.tensor(bb.pos, dtype=pot.dtype, device=dev)
+            v = torch.tensor(v_init, dtype=pot.dtype, device=dev)
+            pot.md_run(x, v, t, bb.box, synth.WATER_MASSES, dt, 1)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, ep, ek = pot.md_run(x, v, t, bb.box, synth.WATER_MASSES, dt, steps)
+            el = time.perf_counter() - t0
+            et = ep + ek
+            print(json.dumps({"report": "md", "form": form, "atoms": bb.n_atoms, "dt_fs": dt, "steps": steps,
+                              "skin_A": skin, "list_builds": pot.md_list_builds,
+                              "ms_per_step": 1e3 * el / steps, "atom_steps_per_s": bb.n_atoms * steps / el,
+                              "max_abs_dE_total_per_atom": float(np.max(np.abs(et - et[0]))) / bb.n_atoms,
+                              "ekin_start": float(ek[0]), "ekin_end": float(ek[-1])}), flush=True)
+            del x, v
         pot.close()
-        del x, v, t
+        del t
         torch.cuda.empty_cache()
     for nt in ((0, 1) if want("cpu_baseline") else ()):  # all threads first: a thread count set once stays set
         cb = cpu_baseline(table, nets, budget_s=30.0 if nt == 1 else 12.0, nthreads=nt)

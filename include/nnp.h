@@ -223,7 +223,13 @@ nnp_status nnp_backward(nnp_handle* h, int n_struct, const int64_t* atom_offsets
  * conservation as its correctness check).  The paper does not name the
  * integrator; this is velocity Verlet:
  *   v += (dt/2) F/m;  x += dt v (then wrapped into [0, L));  F = F(x);  v += (dt/2) F/m.
- * The neighbour list is rebuilt at every force evaluation.
+ * With the default Verlet skin of 0 the neighbour list is rebuilt at every
+ * force evaluation; with a skin > 0 (nnp_set_md_skin) a list of the atoms
+ * within rc + skin is built with a new sort at the first evaluation and
+ * whenever some atom has moved more than skin/2 since the last build, and
+ * every evaluation in between takes its pairs within rc from that list.  Both
+ * give the same forces up to rounding order (a pair within rc at the current
+ * positions is always in the skin list, by the triangle inequality).
  *  n_atoms      atoms of one orthorhombic periodic structure
  *  pos, vel     device [n_atoms][3], positions' type of the handle (FP64 for
  *               NNP_FP64, else FP32), A and A/fs; advanced in place by n_steps
@@ -242,6 +248,20 @@ nnp_status nnp_backward(nnp_handle* h, int n_struct, const int64_t* atom_offsets
 nnp_status nnp_md_run(nnp_handle* h, int64_t n_atoms, void* pos, void* vel, void* forces, const int32_t* types,
                       const double box[3], const double* masses, double dt_fs, int n_steps, double* epot,
                       double* ekin, void* stream);
+
+/*
+ * Verlet skin of the MD driver, in A (finite, >= 0; 0, the default, rebuilds
+ * the neighbour list at every step).  The paper's MD application reuses
+ * neighbour lists between steps in the usual way (Sec. 4, the CabanaMD proxy
+ * app); this sets how far beyond rc the reused list reaches.  Takes effect
+ * at the next nnp_md_run.  NNP_E_ARG for a negative or non-finite skin.
+ */
+nnp_status nnp_set_md_skin(nnp_handle* h, double skin);
+
+/* Neighbour-list builds (sorts plus list builds) of the last nnp_md_run on
+ * this handle: n_steps + 1 with a skin of 0; -1 while another call holds the
+ * handle. */
+int64_t nnp_md_list_builds(const nnp_handle* h);
 
 /*
  * Level of parallelism of the SF and force passes (the paper's Sec. 4.3

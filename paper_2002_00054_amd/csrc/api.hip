@@ -96,6 +96,12 @@ struct nnp_handle {
   std::vector<int64_t> fwd_offs;
   std::vector<double> fwd_boxes;
   std::atomic<int> busy{0};              // an ABI call is running on this handle
+  // MD driver: Verlet skin (A; 0 = rebuild the list at every step), the skin
+  // list's state and capacity, and the neighbour-list builds of the last run
+  double md_skin = 0.0;
+  bool skin_ok = false;
+  int scap = 0;
+  int64_t md_builds = 0;
   // nnp_compute_noalloc: while arena_on, named buffers are carved from the
   // device's static workspace (bump order, reset at every such call) instead
   // of the handle's own allocations, and nothing is allocated.
@@ -301,7 +307,10 @@ struct Batch {
   std::vector<int> struct_chunk;
 };
 
-nnp_status make_batch(nnp_handle* h, int n_struct, const int64_t* offs, const double* boxes, Batch& B) {
+// Batch description; cells have edge >= rcell (default: the cutoff).
+nnp_status make_batch(nnp_handle* h, int n_struct, const int64_t* offs, const double* boxes, Batch& B,
+                      double rcell = 0.0) {
+  if (rcell <= 0.0) rcell = h->rc;
   if (n_struct < 1) return fail(h, NNP_E_ARG, "n_struct must be >= 1");
   if (!offs || !boxes) return fail(h, NNP_E_ARG, "atom_offsets and boxes must not be NULL");
   if (offs[0] != 0) return fail(h, NNP_E_ARG, "atom_offsets[0] must be 0");
@@ -324,7 +333,7 @@ nnp_status make_batch(nnp_handle* h, int n_struct, const int64_t* offs, const do
                                       " must be finite and exceed 2 rc = " + std::to_string(2.0 * h->rc));
       s.L[a] = L;
       s.invL[a] = 1.0 / L;
-      s.ncell[a] = std::max(1, (int)std::floor(L / h->rc));
+      s.ncell[a] = std::max(1, (int)std::floor(L / rcell));
       ncell *= s.ncell[a];
     }
     // Bound the cell count of sparse boxes: coarser cells stay >= rc.
@@ -463,6 +472,7 @@ nnp_status prepare(nnp_handle* h, Common& cm, const IO* pos, const int32_t* type
   if ((st = ensure_t(h, "flags", 4, &a.flags))) return st;
   if (!sort) return NNP_OK;
   h->fwd_valid = false;  // the sorted order, neighbour list, G~ and J store are about to change
+  h->skin_ok = false;    // and the Verlet-skin list with them
   launch_fill_int(a.flags, 4, 0, stream);
   launch_bin_sort<IO>(a, pos, stream);
   return NNP_OK;
@@ -643,13 +653,113 @@ bool fwd_reusable(nnp_handle* h, Common& cm, const IO* pos, const int32_t* types
   return h->h_flags[3] == 0;
 }
 
+// Buffers of one forward evaluation (sorted order unless stated).
+template <int P>
+struct FwdBufs {
+  using IO = typename Types<P>::IO;
+  using FAcc = typename Types<P>::FAcc;
+  IO *G = nullptr, *C = nullptr, *Ei_s = nullptr;
+  FAcc* F_s = nullptr;
+  double *Ei_o = nullptr, *partial = nullptr, *energies = nullptr;  // Ei_o in caller order
+};
+
+template <int P>
+nnp_status fwd_buffers(nnp_handle* h, const Common& cm, int n_struct, FwdBufs<P>& b) {
+  nnp_status st;
+  const int64_t n1 = std::max<int64_t>(cm.B.n, 1);
+  if ((st = ensure_t(h, "G", (size_t)n1 * LD, &b.G))) return st;
+  if ((st = ensure_t(h, "C", (size_t)n1 * LD, &b.C))) return st;
+  if ((st = ensure_t(h, "Ei_s", n1, &b.Ei_s))) return st;
+  if ((st = ensure_t(h, "F_s", (size_t)n1 * 3, &b.F_s))) return st;
+  if ((st = ensure_t(h, "Ei_o", n1, &b.Ei_o))) return st;
+  if ((st = ensure_t(h, "partial", std::max<size_t>(cm.B.chunk_lo.size(), 1), &b.partial))) return st;
+  if ((st = ensure_t(h, "energies", n_struct, &b.energies))) return st;
+  return NNP_OK;
+}
+
+// Everything after the neighbour list (held in cm, with h->lcap set): SF,
+// networks and dE/dG, forces, outputs in the caller's order and the energies.
+template <int P>
+nnp_status evaluate(nnp_handle* h, Common& cm, Marks& mk, const FwdBufs<P>& b, int n_struct,
+                    const typename Types<P>::IO* pos, const int32_t* types, double* energies_dev, double* energy_host,
+                    void* ei_v, void* f_v, hipStream_t stream, bool remember) {
+  using T = typename Types<P>::T;
+  using IO = typename Types<P>::IO;
+  using FAcc = typename Types<P>::FAcc;
+  nnp_status st;
+  const int64_t n = cm.B.n;
+  TripArgs<P> ta = trip_args<P>(h, cm);
+  MlpArgs<P> ma;
+  std::memset(&ma, 0, sizeof(ma));
+  ma.n = n;
+  ma.n_el = h->n_el;
+  ma.eoff = cm.bin.eoff;
+  ma.G = b.G;
+  ma.C = b.C;
+  ma.Ei = b.Ei_s;
+  ma.nets = reinterpret_cast<const T*>(h->d_nets);
+  ma.tab = ta.tab;
+  const bool store = use_store<P>(h);
+  if constexpr (P != P_BF16) {
+    if (store) {
+      JacArgs<P> ja;
+      if ((st = jac_setup<P>(h, cm, ja))) return st;
+      ja.G = b.G;
+      launch_jac<P>(ja, stream);
+      mk.mark("sf");
+      launch_fill<FAcc>(b.F_s, n * 3, FAcc(0), stream);
+      launch_mlp<P>(ma, stream);
+      mk.mark("mlp");
+      ja.C = b.C;
+      ja.F = b.F_s;
+      launch_jac_force<P>(ja, stream);
+      mk.mark("force");
+    }
+  }
+  if (!store) {
+    bool flat = false;
+    if ((st = use_flat<P>(h, 0, 1, &flat))) return st;
+    ta.G = b.G;
+    if (flat) launch_flat<P>(0, ta, stream);
+    else launch_triplet<P>(0, h->variant, ta, stream);
+    mk.mark("sf");
+    launch_fill<FAcc>(b.F_s, n * 3, FAcc(0), stream);
+    launch_mlp<P>(ma, stream);
+    mk.mark("mlp");
+    ta.C = b.C;
+    ta.F = b.F_s;
+    if (flat) launch_flat<P>(1, ta, stream);
+    else launch_triplet<P>(1, h->variant, ta, stream);
+    mk.mark("force");
+  }
+  const bool keep = remember || store;
+  if (keep && (st = fwd_remember<IO>(h, cm, pos, types, stream))) return st;
+  launch_unpermute<IO, FAcc>(n, cm.bin.perm, b.Ei_s, b.F_s, b.Ei_o, reinterpret_cast<IO*>(ei_v),
+                             reinterpret_cast<IO*>(f_v), stream);
+  launch_energy(b.Ei_o, cm.d_clo, cm.d_chi, (int)cm.B.chunk_lo.size(), cm.d_sc, n_struct, b.partial, b.energies,
+                stream);
+  if (energies_dev)
+    NNP_HIP(h, hipMemcpyAsync(energies_dev, b.energies, n_struct * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  if (energy_host)
+    NNP_HIP(h, hipMemcpyAsync(h->h_energy, b.energies, sizeof(double), hipMemcpyDeviceToHost, stream));
+  mk.mark("finish");
+  if ((st = check_launch(h, "forward"))) return st;
+  // Device outputs are ready in stream order; the host waits only for a
+  // host energy or for the profiling events.
+  if (energy_host || h->prof) NNP_HIP(h, hipStreamSynchronize(stream));
+  if (energy_host) *energy_host = *h->h_energy;
+  mk.finish();
+  h->has_forward = true;
+  h->fwd_valid = keep;
+  return NNP_OK;
+}
+
 template <int P>
 nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void* pos_v, const int32_t* types,
                    const double* boxes, double* energies_dev, double* energy_host, void* ei_v, void* f_v,
                    hipStream_t stream, bool remember = false) {
   using T = typename Types<P>::T;
   using IO = typename Types<P>::IO;
-  using FAcc = typename Types<P>::FAcc;
   Common cm;
   nnp_status st;
   if ((st = make_batch(h, n_struct, offs, boxes, cm.B))) return st;
@@ -661,86 +771,97 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
   (void)hipGetLastError();
   if ((st = prepare<IO>(h, cm, pos, types, stream))) return st;
   mk.mark("bin_sort");
-  IO *G, *C, *Ei_s;
-  FAcc* F_s;
-  double *Ei_o, *partial, *energies;
-  const int64_t n1 = std::max<int64_t>(n, 1);
-  if ((st = ensure_t(h, "G", (size_t)n1 * LD, &G))) return st;
-  if ((st = ensure_t(h, "C", (size_t)n1 * LD, &C))) return st;
-  if ((st = ensure_t(h, "Ei_s", n1, &Ei_s))) return st;
-  if ((st = ensure_t(h, "F_s", (size_t)n1 * 3, &F_s))) return st;
-  if ((st = ensure_t(h, "Ei_o", n1, &Ei_o))) return st;
-  if ((st = ensure_t(h, "partial", std::max<size_t>(cm.B.chunk_lo.size(), 1), &partial))) return st;
-  if ((st = ensure_t(h, "energies", n_struct, &energies))) return st;
+  FwdBufs<P> bufs;
+  if ((st = fwd_buffers<P>(h, cm, n_struct, bufs))) return st;
   for (int attempt = 0; attempt < 8; ++attempt) {
     if ((st = build_neighbors<T>(h, cm, stream))) return st;
     const int r = check_flags(h, stream, cm, &st);
     if (r < 0) return st;
     if (r > 0) continue;  // capacity grew: rebuild the neighbour list
     mk.mark("neighbors");
-    TripArgs<P> ta = trip_args<P>(h, cm);
-    MlpArgs<P> ma;
-    std::memset(&ma, 0, sizeof(ma));
-    ma.n = n;
-    ma.n_el = h->n_el;
-    ma.eoff = cm.bin.eoff;
-    ma.G = G;
-    ma.C = C;
-    ma.Ei = Ei_s;
-    ma.nets = reinterpret_cast<const T*>(h->d_nets);
-    ma.tab = ta.tab;
-    const bool store = use_store<P>(h);
-    if constexpr (P != P_BF16) {
-      if (store) {
-        JacArgs<P> ja;
-        if ((st = jac_setup<P>(h, cm, ja))) return st;
-        ja.G = G;
-        launch_jac<P>(ja, stream);
-        mk.mark("sf");
-        launch_fill<FAcc>(F_s, n * 3, FAcc(0), stream);
-        launch_mlp<P>(ma, stream);
-        mk.mark("mlp");
-        ja.C = C;
-        ja.F = F_s;
-        launch_jac_force<P>(ja, stream);
-        mk.mark("force");
+    return evaluate<P>(h, cm, mk, bufs, n_struct, pos, types, energies_dev, energy_host, ei_v, f_v, stream, remember);
+  }
+  return fail(h, NNP_E_STATE, "neighbour capacity did not converge");
+}
+
+// Forward evaluation of one structure with a Verlet-skin neighbour list (the
+// MD driver): the list of atoms within rc + skin is built with the sorted
+// order and reused while no atom has moved more than skin/2 since; each call
+// re-gathers the sorted positions and extracts the rows within rc from it.
+// The skin list is rebuilt (with a new sort) when the displacement test
+// fails or h->skin_ok is false.
+template <int P>
+nnp_status forward_skin(nnp_handle* h, int64_t n, const void* pos_v, const int32_t* types, const double box[3],
+                        double* energies_dev, void* f_v, hipStream_t stream) {
+  using T = typename Types<P>::T;
+  using IO = typename Types<P>::IO;
+  Common cm;
+  nnp_status st;
+  const int64_t offs[2] = {0, n};
+  const double rs = h->rc + h->md_skin;
+  if ((st = make_batch(h, 1, offs, box, cm.B, rs))) return st;
+  const IO* pos = reinterpret_cast<const IO*>(pos_v);
+  h->cap = initial_cap(h, cm.B);
+  {
+    const double rho = (double)n / (box[0] * box[1] * box[2]);
+    int sc = (int)std::ceil(rho * 4.0 / 3.0 * M_PI * rs * rs * rs * 1.2 + 16.0);
+    sc = (sc + 15) / 16 * 16;
+    h->scap = std::max(h->scap, std::max(sc, 32));
+  }
+  Marks mk(h, stream);
+  (void)hipGetLastError();
+  FwdBufs<P> bufs;
+  if ((st = fwd_buffers<P>(h, cm, 1, bufs))) return st;
+  const int64_t n1 = std::max<int64_t>(n, 1);
+  double4* ref = nullptr;
+  if ((st = ensure_t(h, "skin_ref", n1, &ref))) return st;
+  for (int attempt = 0; attempt < 16; ++attempt) {
+    int* snbr = nullptr;
+    int4* snnb = nullptr;
+    if ((st = ensure_t(h, "skin_nbr", (size_t)n1 * h->scap, &snbr))) return st;
+    if ((st = ensure_t(h, "skin_nnb", n1, &snnb))) return st;
+    if (!h->skin_ok) {
+      if ((st = prepare<IO>(h, cm, pos, types, stream))) return st;  // clears the flags
+      int* cmax = nullptr;
+      if ((st = ensure_t(h, "cmax", std::max(cm.B.total_cells, 1), &cmax))) return st;
+      launch_neighbor_index(cm.bin, rs, h->scap, snbr, snnb, cmax, stream);
+      NNP_HIP(h, hipMemcpyAsync(h->h_flags, cm.bin.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, stream));
+      NNP_HIP(h, hipStreamSynchronize(stream));
+      if (h->h_flags[0] & 1) return fail(h, NNP_E_TYPE, "atom type outside [0, n_el)");
+      if (h->h_flags[0] & 2) return fail(h, NNP_E_ARG, "non-finite atom position (NaN or infinity)");
+      if (h->h_flags[1] > h->scap) {  // skin capacity too small: grow it and build again
+        h->scap = ((int)std::ceil(h->h_flags[1] * 1.15) + 8 + 15) / 16 * 16;
+        continue;
       }
+      if (n > 0) NNP_HIP(h, hipMemcpyAsync(ref, cm.bin.pos4, (size_t)n * sizeof(double4), hipMemcpyDeviceToDevice, stream));
+      h->skin_ok = true;
+      ++h->md_builds;
+      mk.mark("skin_build");
+      launch_fill_int(cm.bin.flags, 4, 0, stream);
+    } else {
+      if ((st = prepare<IO>(h, cm, pos, types, stream, false))) return st;  // binds the kept sorted order
+      launch_fill_int(cm.bin.flags, 4, 0, stream);
+      launch_regather<IO>(cm.bin, pos, ref, 0.5 * h->md_skin, stream);
+      mk.mark("regather");
     }
-    if (!store) {
-      bool flat = false;
-      if ((st = use_flat<P>(h, 0, 1, &flat))) return st;
-      ta.G = G;
-      if (flat) launch_flat<P>(0, ta, stream);
-      else launch_triplet<P>(0, h->variant, ta, stream);
-      mk.mark("sf");
-      launch_fill<FAcc>(F_s, n * 3, FAcc(0), stream);
-      launch_mlp<P>(ma, stream);
-      mk.mark("mlp");
-      ta.C = C;
-      ta.F = F_s;
-      if (flat) launch_flat<P>(1, ta, stream);
-      else launch_triplet<P>(1, h->variant, ta, stream);
-      mk.mark("force");
+    if ((st = bind_neighbors<T>(h, cm))) return st;
+    launch_refresh<T>(cm.bin, snbr, snnb, h->scap, h->rc, h->cap, reinterpret_cast<typename Vec4<T>::type*>(cm.nbr),
+                      cm.nnb, stream);
+    NNP_HIP(h, hipMemcpyAsync(h->h_flags, cm.bin.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, stream));
+    NNP_HIP(h, hipStreamSynchronize(stream));
+    if (h->h_flags[0] & 2) return fail(h, NNP_E_ARG, "non-finite atom position (NaN or infinity)");
+    if (h->h_flags[0] & 4) {  // an atom moved more than skin/2: new sort and skin list
+      h->skin_ok = false;
+      continue;
     }
-    const bool keep = remember || store;
-    if (keep && (st = fwd_remember<IO>(h, cm, pos, types, stream))) return st;
-    launch_unpermute<IO, FAcc>(n, cm.bin.perm, Ei_s, F_s, Ei_o, reinterpret_cast<IO*>(ei_v),
-                               reinterpret_cast<IO*>(f_v), stream);
-    launch_energy(Ei_o, cm.d_clo, cm.d_chi, (int)cm.B.chunk_lo.size(), cm.d_sc, n_struct, partial, energies, stream);
-    if (energies_dev)
-      NNP_HIP(h, hipMemcpyAsync(energies_dev, energies, n_struct * sizeof(double), hipMemcpyDeviceToDevice, stream));
-    if (energy_host)
-      NNP_HIP(h, hipMemcpyAsync(h->h_energy, energies, sizeof(double), hipMemcpyDeviceToHost, stream));
-    mk.mark("finish");
-    if ((st = check_launch(h, "forward"))) return st;
-    // Device outputs are ready in stream order; the host waits only for a
-    // host energy or for the profiling events.
-    if (energy_host || h->prof) NNP_HIP(h, hipStreamSynchronize(stream));
-    if (energy_host) *energy_host = *h->h_energy;
-    mk.finish();
-    h->has_forward = true;
-    h->fwd_valid = keep;
-    return NNP_OK;
+    if (h->h_flags[1] > h->cap) {
+      const int nc = (int)std::ceil(h->h_flags[1] * 1.15) + 8;
+      h->cap = (nc + 15) / 16 * 16;
+      continue;  // the next round re-gathers (unchanged) and refreshes into the larger rows
+    }
+    h->lcap = std::min(h->cap, (std::max(h->h_flags[2], 1) + 7) / 8 * 8);
+    mk.mark("neighbors");
+    return evaluate<P>(h, cm, mk, bufs, 1, pos, types, energies_dev, nullptr, nullptr, f_v, stream, false);
   }
   return fail(h, NNP_E_STATE, "neighbour capacity did not converge");
 }
@@ -900,11 +1021,18 @@ nnp_status md_run(nnp_handle* h, int64_t n, void* pos_v, void* vel_v, void* f_v,
   if ((st = ensure_t(h, "md_ekin", (size_t)n_steps + 1, &k_dev))) return st;
   if ((st = ensure_t(h, "md_part", (size_t)md_blocks(n), &part))) return st;
   const int64_t offs[2] = {0, n};
-  if ((st = forward<P>(h, 1, offs, pos, types, box, e_dev, nullptr, nullptr, F, stream))) return st;
+  h->skin_ok = false;  // the first evaluation builds the skin list
+  h->md_builds = 0;
+  auto force_at = [&](double* e_out) -> nnp_status {
+    if (h->md_skin > 0.0) return forward_skin<P>(h, n, pos, types, box, e_out, F, stream);
+    ++h->md_builds;
+    return forward<P>(h, 1, offs, pos, types, box, e_out, nullptr, nullptr, F, stream);
+  };
+  if ((st = force_at(e_dev))) return st;
   launch_kick_ke<IO>(n, vel, F, types, m, false, part, k_dev, stream);
   for (int s = 1; s <= n_steps; ++s) {
     launch_kick_drift<IO>(n, pos, vel, F, types, m, stream);
-    if ((st = forward<P>(h, 1, offs, pos, types, box, e_dev + s, nullptr, nullptr, F, stream))) return st;
+    if ((st = force_at(e_dev + s))) return st;
     launch_kick_ke<IO>(n, vel, F, types, m, true, part, k_dev + s, stream);
   }
   if ((st = check_launch(h, "md"))) return st;
@@ -1295,6 +1423,23 @@ nnp_status nnp_md_run(nnp_handle* h, int64_t n_atoms, void* pos, void* vel, void
     case NNP_FP32: return md_run<P_FP32>(h, n_atoms, pos, vel, forces, types, box, masses, dt_fs, n_steps, epot, ekin, s);
     default: return md_run<P_BF16>(h, n_atoms, pos, vel, forces, types, box, masses, dt_fs, n_steps, epot, ekin, s);
   }
+}
+
+nnp_status nnp_set_md_skin(nnp_handle* h, double skin) {
+  if (!h) return NNP_E_ARG;
+  Claim claim(h);
+  if (!claim.ok) return NNP_E_STATE;
+  if (!(std::isfinite(skin) && skin >= 0.0)) return fail(h, NNP_E_ARG, "skin must be finite and >= 0");
+  h->md_skin = skin;
+  h->skin_ok = false;
+  return NNP_OK;
+}
+
+int64_t nnp_md_list_builds(const nnp_handle* h) {
+  if (!h) return -1;
+  Claim claim(const_cast<nnp_handle*>(h));
+  if (!claim.ok) return -1;
+  return h->md_builds;
 }
 
 nnp_status nnp_set_parallelism(nnp_handle* h, int mode) {

@@ -40,6 +40,16 @@ __device__ inline float4 make_entry(double dx, double dy, double dz, int j, floa
 __device__ inline double4 make_entry(double dx, double dy, double dz, int j, double) {
   return make_double4(dx, dy, dz, __longlong_as_double((long long)j));
 }
+// Entries of type E: displacement + index (float4, double4) or the index alone (int).
+__host__ __device__ inline int entry_index(int e) { return e; }
+template <class E> __device__ inline E make_entry_as(double dx, double dy, double dz, int j);
+template <> __device__ inline float4 make_entry_as<float4>(double dx, double dy, double dz, int j) {
+  return make_entry(dx, dy, dz, j, 0.f);
+}
+template <> __device__ inline double4 make_entry_as<double4>(double dx, double dy, double dz, int j) {
+  return make_entry(dx, dy, dz, j, 0.0);
+}
+template <> __device__ inline int make_entry_as<int>(double, double, double, int j) { return j; }
 
 template <int P> struct Types;
 template <> struct Types<P_FP64> { using T = double; using Acc = double; using FAcc = double; using IO = double; };

@@ -221,12 +221,12 @@ __device__ inline int centre_of(int ci, const int* cbeg, const int* clen, int n_
   return -1;
 }
 
-template <class T>
+template <class E>
 __global__ void __launch_bounds__(256) k_neighbors(const double4* __restrict__ pos4, const DevStruct* __restrict__ st,
                                                    int n_struct, const int* __restrict__ start, int n_el,
-                                                   int total_cells, double rc2, int cap,
-                                                   typename Vec4<T>::type* __restrict__ nbr, int4* __restrict__ nnb,
-                                                   int* __restrict__ flags, int* __restrict__ cmax) {
+                                                   int total_cells, double rc2, int cap, E* __restrict__ nbr,
+                                                   int4* __restrict__ nnb, int* __restrict__ flags,
+                                                   int* __restrict__ cmax) {
   __shared__ double4 sp[NB_TILE];
   __shared__ int seg_first[MAX_EL * 27];
   __shared__ int seg_off[MAX_EL * 27 + 1];
@@ -332,7 +332,7 @@ __global__ void __launch_bounds__(256) k_neighbors(const double4* __restrict__ p
         const int c = cidx[ci];
         const double4 p = cpos[ci];
         int tot = c_tot[ci];
-        typename Vec4<T>::type* row = nbr + (int64_t)c * cap;
+        E* row = nbr + (int64_t)c * cap;
         for (int u0 = 0; u0 < tl; u0 += WAVE) {
           const int u = u0 + lane;
           bool pass = false;
@@ -354,7 +354,7 @@ __global__ void __launch_bounds__(256) k_neighbors(const double4* __restrict__ p
           const unsigned long long msk = __builtin_amdgcn_ballot_w64(pass);
           const int rank = tot + lanes_below(msk);
           const bool keep = pass && rank < cap;
-          if (keep) row[rank] = make_entry(dx, dy, dz, sidx, T(0));
+          if (keep) row[rank] = make_entry_as<E>(dx, dy, dz, sidx);
           // an element block starting inside this step: passing candidates before it
           const int g0 = t0 + u0;
           for (int e = 1; e < n_el; ++e) {
@@ -399,6 +399,110 @@ __global__ void __launch_bounds__(256) k_max_count(int ncells, const int* __rest
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) atomicMax(&flags[2], max(max(red[0], red[1]), max(red[2], red[3])));
+}
+
+// Verlet-skin reuse of a neighbour list (molecular dynamics).  The skin
+// list holds, for every sorted atom, the indices of the atoms within
+// rc + skin at its last build (element-grouped, as above); while no atom has
+// moved more than skin/2 since then, every pair within rc is in it, because
+// the minimum-image distance obeys the triangle inequality.
+//
+// k_regather: sorted positions refreshed from the caller's positions in the
+// kept sorted order (wrapped in FP64, ids kept), and each atom's
+// minimum-image displacement since the build tested against lim2 =
+// (skin/2)^2: flags[0] bit 2 if any atom moved farther (the skin list must
+// be rebuilt), bit 1 if a coordinate is not finite.
+template <class TIn>
+__global__ void __launch_bounds__(256) k_regather(int64_t n, const TIn* __restrict__ pos,
+                                                  const DevStruct* __restrict__ st, const int* __restrict__ perm,
+                                                  double4* __restrict__ pos4, const double4* __restrict__ ref,
+                                                  double lim2, int* __restrict__ flags) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool far = false, bad = false;
+  if (s < n) {
+    const int64_t i = perm[s];
+    double4 p = pos4[s];
+    const DevStruct& S = st[struct_of(p.w)];
+    const double x = (double)pos[3 * i + 0], y = (double)pos[3 * i + 1], z = (double)pos[3 * i + 2];
+    bad = !(isfinite(x) && isfinite(y) && isfinite(z));
+    p.x = wrap_coord(x, S.L[0], S.invL[0]);
+    p.y = wrap_coord(y, S.L[1], S.invL[1]);
+    p.z = wrap_coord(z, S.L[2], S.invL[2]);
+    const double4 r = ref[s];
+    double dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z;
+    dx -= S.L[0] * rint(dx * S.invL[0]);
+    dy -= S.L[1] * rint(dy * S.invL[1]);
+    dz -= S.L[2] * rint(dz * S.invL[2]);
+    far = dx * dx + dy * dy + dz * dz > lim2;
+    pos4[s] = p;
+  }
+  const unsigned long long fm = __builtin_amdgcn_ballot_w64(far), bm = __builtin_amdgcn_ballot_w64(bad);
+  if ((threadIdx.x & 63) == 0) {
+    if (fm) atomicOr(&flags[0], 4);
+    if (bm) atomicOr(&flags[0], 2);
+  }
+}
+
+// k_refresh: the rows of (r_j - r_i, j) entries within rc, read from the
+// skin list and the current positions (minimum image in FP64), one wave per
+// centre, compacted by ballot so that the element grouping is kept.  As in
+// the build: at most cap entries per row, flags[1] the largest count beyond
+// cap, flags[2] the largest count (one atomic per workgroup).
+template <class E>
+__global__ void __launch_bounds__(256) k_refresh(int64_t n, int n_el, const double4* __restrict__ pos4,
+                                                 const DevStruct* __restrict__ st, const int* __restrict__ snbr,
+                                                 const int4* __restrict__ snnb, int scap, double rc2, int cap,
+                                                 E* __restrict__ nbr, int4* __restrict__ nnb,
+                                                 int* __restrict__ flags) {
+  __shared__ int red[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int most = 0;
+  for (int64_t c = (int64_t)blockIdx.x * 4 + wv; c < n; c += (int64_t)gridDim.x * 4) {
+    const double4 p = pos4[c];
+    const DevStruct& S = st[struct_of(p.w)];
+    const int4 sc = snnb[c];
+    const int scnt[MAX_EL] = {sc.x, sc.y, sc.z, sc.w};
+    const int* srow = snbr + c * (int64_t)scap;
+    E* row = nbr + c * (int64_t)cap;
+    int tot = 0, so = 0;
+    int kept[MAX_EL] = {0, 0, 0, 0};
+    for (int f = 0; f < n_el; ++f) {
+      const int before = tot, end = so + scnt[f];
+      for (int t0 = so; t0 < end; t0 += WAVE) {
+        const int t = t0 + lane;
+        bool pass = false;
+        double dx = 0.0, dy = 0.0, dz = 0.0;
+        int j = 0;
+        if (t < end) {
+          j = srow[t];
+          const double4 q = pos4[j];
+          dx = q.x - p.x;
+          dy = q.y - p.y;
+          dz = q.z - p.z;
+          dx -= S.L[0] * rint(dx * S.invL[0]);
+          dy -= S.L[1] * rint(dy * S.invL[1]);
+          dz -= S.L[2] * rint(dz * S.invL[2]);
+          pass = dx * dx + dy * dy + dz * dz < rc2;
+        }
+        const unsigned long long msk = __builtin_amdgcn_ballot_w64(pass);
+        const int rank = tot + lanes_below(msk);
+        if (pass && rank < cap) row[rank] = make_entry_as<E>(dx, dy, dz, j);
+        tot += __popcll(msk);
+      }
+      kept[f] = min(tot, cap) - min(before, cap);
+      so = end;
+    }
+    if (lane == 0) nnb[c] = make_int4(kept[0], kept[1], kept[2], kept[3]);
+    most = max(most, tot);
+  }
+  for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
+  if (lane == 0) red[wv] = most;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int m = max(max(red[0], red[1]), max(red[2], red[3]));
+    atomicMax(&flags[2], m);
+    if (m > cap) atomicMax(&flags[1], m);
+  }
 }
 
 // Work counts of one evaluation, one thread per centre:
@@ -493,17 +597,48 @@ void launch_bin_sort(const BinArgs& a, const TIn* pos, hipStream_t stream) {
 template void launch_bin_sort<float>(const BinArgs&, const float*, hipStream_t);
 template void launch_bin_sort<double>(const BinArgs&, const double*, hipStream_t);
 
-template <class T>
-void launch_neighbors(const BinArgs& a, double rc, int cap, typename Vec4<T>::type* nbr, int4* nnb, int* cmax,
-                      hipStream_t stream) {
+template <class E>
+void launch_neighbors_as(const BinArgs& a, double rc, int cap, E* nbr, int4* nnb, int* cmax, hipStream_t stream) {
   if (a.n == 0) return;
-  hipLaunchKernelGGL(k_neighbors<T>, dim3((unsigned)a.total_cells), dim3(256), 0, stream, a.pos4, a.st, a.n_struct,
+  hipLaunchKernelGGL(k_neighbors<E>, dim3((unsigned)a.total_cells), dim3(256), 0, stream, a.pos4, a.st, a.n_struct,
                      a.start, a.n_el, a.total_cells, rc * rc, cap, nbr, nnb, a.flags, cmax);
   hipLaunchKernelGGL(k_max_count, dim3((unsigned)std::max(1, (a.total_cells + MAXC_PER - 1) / MAXC_PER)), dim3(256), 0,
                      stream, a.total_cells, cmax, a.flags);
 }
+
+template <class T>
+void launch_neighbors(const BinArgs& a, double rc, int cap, typename Vec4<T>::type* nbr, int4* nnb, int* cmax,
+                      hipStream_t stream) {
+  launch_neighbors_as<typename Vec4<T>::type>(a, rc, cap, nbr, nnb, cmax, stream);
+}
 template void launch_neighbors<float>(const BinArgs&, double, int, float4*, int4*, int*, hipStream_t);
 template void launch_neighbors<double>(const BinArgs&, double, int, double4*, int4*, int*, hipStream_t);
+
+void launch_neighbor_index(const BinArgs& a, double rc, int cap, int* nbr, int4* nnb, int* cmax, hipStream_t stream) {
+  launch_neighbors_as<int>(a, rc, cap, nbr, nnb, cmax, stream);
+}
+
+template <class TIn>
+void launch_regather(const BinArgs& a, const TIn* pos, const double4* ref, double lim, hipStream_t stream) {
+  if (a.n == 0) return;
+  hipLaunchKernelGGL(k_regather<TIn>, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, stream, a.n, pos, a.st,
+                     a.perm, a.pos4, ref, lim * lim, a.flags);
+}
+template void launch_regather<float>(const BinArgs&, const float*, const double4*, double, hipStream_t);
+template void launch_regather<double>(const BinArgs&, const double*, const double4*, double, hipStream_t);
+
+template <class T>
+void launch_refresh(const BinArgs& a, const int* snbr, const int4* snnb, int scap, double rc, int cap,
+                    typename Vec4<T>::type* nbr, int4* nnb, hipStream_t stream) {
+  if (a.n == 0) return;
+  const unsigned g = (unsigned)std::min<int64_t>((a.n + 3) / 4, 16384);
+  hipLaunchKernelGGL(k_refresh<typename Vec4<T>::type>, dim3(g), dim3(256), 0, stream, a.n, a.n_el, a.pos4, a.st,
+                     snbr, snnb, scap, rc * rc, cap, nbr, nnb, a.flags);
+}
+template void launch_refresh<float>(const BinArgs&, const int*, const int4*, int, double, int, float4*, int4*,
+                                    hipStream_t);
+template void launch_refresh<double>(const BinArgs&, const int*, const int4*, int, double, int, double4*, int4*,
+                                     hipStream_t);
 
 template <class T>
 void launch_count_terms(const BinArgs& a, const typename Vec4<T>::type* nbr, const int4* nnb, int cap,

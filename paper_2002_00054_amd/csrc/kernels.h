@@ -23,7 +23,8 @@ struct BinArgs {
   int* perm_raw;             // [n] the scatter's order within each bin, before the bin sort
   double4* pos4;             // [n] sorted wrapped positions + ids
   int* eoff;                 // [n_el + 1] element offsets of the sorted order
-  int* flags;                // [0] bit 0 bad type, bit 1 non-finite position, [1] max neighbour count beyond cap, [2] max count
+  int* flags;                // [0] bit 0 bad type, bit 1 non-finite position, bit 2 skin exceeded;
+                             // [1] max neighbour count beyond cap, [2] max count, [3] inputs differ
 };
 
 void launch_fill_int(int* p, int64_t n, int v, hipStream_t stream);
@@ -33,6 +34,16 @@ void launch_bin_sort(const BinArgs& a, const TIn* pos, hipStream_t stream);
 template <class T>
 void launch_neighbors(const BinArgs& a, double rc, int cap, typename Vec4<T>::type* nbr, int4* nnb, int* cmax,
                       hipStream_t stream);
+// Rows of neighbour indices alone (the Verlet-skin list of the MD driver).
+void launch_neighbor_index(const BinArgs& a, double rc, int cap, int* nbr, int4* nnb, int* cmax, hipStream_t stream);
+// Sorted positions from the caller's in the kept order; flags[0] bit 2 if any
+// atom moved more than lim from ref (its sorted position at the skin build).
+template <class TIn>
+void launch_regather(const BinArgs& a, const TIn* pos, const double4* ref, double lim, hipStream_t stream);
+// Rows of (dx, dy, dz, j) entries within rc from the skin list (scap slots per row).
+template <class T>
+void launch_refresh(const BinArgs& a, const int* snbr, const int4* snnb, int scap, double rc, int cap,
+                    typename Vec4<T>::type* nbr, int4* nnb, hipStream_t stream);
 // Angular / radial SF counts per (centre, class) and (centre, neighbour element).
 struct CountTab {
   int ang[MAX_EL][MAX_CLS];

@@ -24,7 +24,8 @@ STATUS = {0: "NNP_OK", -1: "NNP_E_ARG", -2: "NNP_E_BOX", -3: "NNP_E_TYPE", -4: "
 EXPORTS = ("nnp_create", "nnp_compute", "nnp_compute_noalloc", "nnp_compute_batch", "nnp_backward", "nnp_n_params",
            "nnp_set_params",
            "nnp_get_params", "nnp_set_profiling", "nnp_last_timings", "nnp_neighbor_capacity",
-           "nnp_set_neighbor_capacity", "nnp_count_work", "nnp_md_run", "nnp_set_parallelism",
+           "nnp_set_neighbor_capacity", "nnp_count_work", "nnp_md_run", "nnp_set_md_skin", "nnp_md_list_builds",
+           "nnp_set_parallelism",
            "nnp_set_derivative_mode",
            "nnp_workspace_bytes",
            "nnp_destroy", "nnp_last_error")
@@ -82,6 +83,9 @@ def load_library(path: str = LIB_PATH):
     L.nnp_set_neighbor_capacity.argtypes = [vp, C.c_int]
     L.nnp_count_work.argtypes = [vp, i64, vp, vp, dp, C.POINTER(i64), vp]
     L.nnp_md_run.argtypes = [vp, i64, vp, vp, vp, vp, dp, dp, C.c_double, C.c_int, dp, dp, vp]
+    L.nnp_set_md_skin.argtypes = [vp, C.c_double]
+    L.nnp_md_list_builds.argtypes = [vp]
+    L.nnp_md_list_builds.restype = i64
     L.nnp_set_parallelism.argtypes = [vp, C.c_int]
     L.nnp_set_derivative_mode.argtypes = [vp, C.c_int]
     L.nnp_workspace_bytes.argtypes = [vp]
@@ -93,7 +97,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("nnp_create", "nnp_compute", "nnp_compute_noalloc", "nnp_compute_batch", "nnp_backward",
                  "nnp_set_params",
                  "nnp_get_params", "nnp_set_profiling", "nnp_set_neighbor_capacity", "nnp_last_timings",
-                 "nnp_neighbor_capacity", "nnp_count_work", "nnp_md_run", "nnp_set_parallelism",
+                 "nnp_neighbor_capacity", "nnp_count_work", "nnp_md_run", "nnp_set_md_skin", "nnp_set_parallelism",
                  "nnp_set_derivative_mode"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -294,6 +298,15 @@ class Potential:
                                        int(n_steps), ep.ctypes.data_as(C.POINTER(C.c_double)),
                                        ek.ctypes.data_as(C.POINTER(C.c_double)), _stream_ptr(stream)))
         return f, ep, ek
+
+    def set_md_skin(self, skin: float):
+        """Verlet skin (A) of md_run: 0 rebuilds the neighbour list every step."""
+        self._check(self._L.nnp_set_md_skin(self._h, float(skin)))
+
+    @property
+    def md_list_builds(self) -> int:
+        """Neighbour-list builds of the last md_run."""
+        return int(self._L.nnp_md_list_builds(self._h))
 
     def count_work(self, pos, types, box, stream=None) -> dict:
         """Neighbour entries, candidate neighbour pairs and triplet terms of
