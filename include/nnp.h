@@ -286,6 +286,29 @@ typedef enum { NNP_PAR_AUTO = 0, NNP_PAR_WAVE = 1, NNP_PAR_THREAD = 2 } nnp_para
 nnp_status nnp_set_parallelism(nnp_handle* h, int mode);
 
 /*
+ * Layout of the neighbour list that the wave-level SF, force and
+ * force-adjoint passes read (the data-layout question of Sec. 4.3 and
+ * Figs. 6-7, asked here of the one structure the pair passes loop over).
+ *  NNP_LIST_PADDED   (default) rows of cap slots per atom; an entry is the
+ *                    minimum-image displacement r_j - r_i, formed in FP64 and
+ *                    rounded once to the arithmetic type, and the index j
+ *                    (16 bytes in FP32 and BF16, 32 in FP64).
+ *  NNP_LIST_INDEX    rows of cap slots holding the index j alone (4 bytes);
+ *                    the pair passes gather the sorted FP64 positions and
+ *                    form the same displacement themselves.
+ *  NNP_LIST_COMPACT  displacement entries in rows without padding: the build
+ *                    counts first, scans the row lengths into offsets (the
+ *                    host waits for the total) and writes each row at its
+ *                    offset.
+ * Results equal those of the padded layout up to rounding order.  The
+ * thread-level passes, the stored-Jacobian form, the Verlet-skin MD path and
+ * nnp_count_work always use the padded layout; a call that ends up at the
+ * thread level rebuilds its list padded.  An unknown layout is NNP_E_ARG.
+ */
+typedef enum { NNP_LIST_PADDED = 0, NNP_LIST_INDEX = 1, NNP_LIST_COMPACT = 2 } nnp_list_layout;
+nnp_status nnp_set_list_layout(nnp_handle* h, int layout);
+
+/*
  * How the differentiation form obtains the SF derivatives dG_is/dr_m.
  *  NNP_DERIV_RECOMPUTE  (default) the force pass and nnp_backward recompute
  *                       them from the neighbour list, as the paper does

@@ -98,6 +98,9 @@ struct nnp_handle {
   std::atomic<int> busy{0};              // an ABI call is running on this handle
   // MD driver: Verlet skin (A; 0 = rebuild the list at every step), the skin
   // list's state and capacity, and the neighbour-list builds of the last run
+  int list_layout = NNP_LIST_PADDED;     // of the wave-level passes with recomputed derivatives
+  size_t compact_entries = 0;            // entries of the last compact list
+  int fwd_layout = NNP_LIST_PADDED;      // layout of the list the last batch forward left
   double md_skin = 0.0;
   bool skin_ok = false;
   int scap = 0;
@@ -413,7 +416,10 @@ struct Common {
   int64_t* d_chi = nullptr;
   int* d_sc = nullptr;
   BinArgs bin;
-  void* nbr = nullptr;   // [n][cap] Vec4<T> entries of the form's arithmetic type
+  int layout = NNP_LIST_PADDED;
+  void* nbr = nullptr;   // [n][cap] Vec4<T> entries of the form's arithmetic type (compact: at roff)
+  int* idx = nullptr;    // index layout: [n][cap] neighbour indices
+  int* roff = nullptr;   // compact layout: [n + 1] row offsets
   int4* nnb = nullptr;
 };
 
@@ -478,31 +484,68 @@ nnp_status prepare(nnp_handle* h, Common& cm, const IO* pos, const int32_t* type
   return NNP_OK;
 }
 
+// Binds the neighbour list of the given layout that the workspace holds
+// (padded entries, index entries, or compact entries with their offsets).
 template <class T>
-nnp_status bind_neighbors(nnp_handle* h, Common& cm) {
+nnp_status bind_neighbors(nnp_handle* h, Common& cm, int layout = NNP_LIST_PADDED) {
   using E = typename Vec4<T>::type;
   nnp_status st;
   const int64_t n = std::max<int64_t>(cm.B.n, 1);
-  E* nbr = nullptr;
-  if ((st = ensure_t(h, "nbr", (size_t)n * h->cap, &nbr))) return st;
+  cm.layout = layout;
+  cm.nbr = nullptr;
+  cm.idx = nullptr;
+  cm.roff = nullptr;
   if ((st = ensure_t(h, "nnb", n, &cm.nnb))) return st;
+  if (layout == NNP_LIST_INDEX) return ensure_t(h, "nbr_idx", (size_t)n * h->cap, &cm.idx);
+  E* nbr = nullptr;
+  if (layout == NNP_LIST_COMPACT) {
+    if ((st = ensure_t(h, "roff", (size_t)n + 1, &cm.roff))) return st;
+    if ((st = ensure_t(h, "nbr", std::max<size_t>(h->compact_entries, 1), &nbr))) return st;
+  } else if ((st = ensure_t(h, "nbr", (size_t)n * h->cap, &nbr))) {
+    return st;
+  }
   cm.nbr = nbr;
   return NNP_OK;
 }
 
+// The neighbour build in the given layout.  The compact layout counts first,
+// scans the row lengths and reads the total back (a host wait) to size the
+// list, then writes it; its rows never overflow.
 template <class T>
-nnp_status build_neighbors(nnp_handle* h, Common& cm, hipStream_t stream) {
+nnp_status build_neighbors(nnp_handle* h, Common& cm, hipStream_t stream, int layout = NNP_LIST_PADDED) {
   using E = typename Vec4<T>::type;
   nnp_status st;
   const int64_t n = std::max<int64_t>(cm.B.n, 1);
-  E* nbr = nullptr;
   int* cmax = nullptr;
-  if ((st = ensure_t(h, "nbr", (size_t)n * h->cap, &nbr))) return st;
-  if ((st = ensure_t(h, "nnb", n, &cm.nnb))) return st;
   if ((st = ensure_t(h, "cmax", std::max(cm.B.total_cells, 1), &cmax))) return st;
-  cm.nbr = nbr;
   launch_fill_int(cm.bin.flags + 1, 2, 0, stream);
-  launch_neighbors<T>(cm.bin, h->rc, h->cap, nbr, cm.nnb, cmax, stream);
+  if (layout == NNP_LIST_COMPACT) {
+    int *len, *tmp, *part, *roff;
+    int4* nnb;
+    if ((st = ensure_t(h, "nnb", n, &nnb))) return st;
+    if ((st = ensure_t(h, "roff", (size_t)n + 1, &roff))) return st;
+    if ((st = ensure_t(h, "row_len", n, &len))) return st;
+    if ((st = ensure_t(h, "row_tmp", n, &tmp))) return st;
+    if ((st = ensure_t(h, "row_part", n / 4096 + 1, &part))) return st;
+    if (cm.B.n > 0) {
+      launch_neighbor_counts<T>(cm.bin, h->rc, nnb, cmax, stream);
+      launch_row_offsets(cm.B.n, nnb, len, roff, tmp, part, stream);
+      int total = 0;
+      NNP_HIP(h, hipMemcpyAsync(h->h_flags, roff + cm.B.n, sizeof(int), hipMemcpyDeviceToHost, stream));
+      NNP_HIP(h, hipStreamSynchronize(stream));
+      total = h->h_flags[0];
+      if (total < 0) return fail(h, NNP_E_ARG, "too many neighbour entries for the compact layout");
+      h->compact_entries = (size_t)total;
+    } else {
+      h->compact_entries = 0;
+    }
+    if ((st = bind_neighbors<T>(h, cm, layout))) return st;
+    launch_neighbors_compact<T>(cm.bin, h->rc, cm.roff, reinterpret_cast<E*>(cm.nbr), cm.nnb, cmax, stream);
+    return NNP_OK;
+  }
+  if ((st = bind_neighbors<T>(h, cm, layout))) return st;
+  if (layout == NNP_LIST_INDEX) launch_neighbor_index(cm.bin, h->rc, h->cap, cm.idx, cm.nnb, cmax, stream);
+  else launch_neighbors<T>(cm.bin, h->rc, h->cap, reinterpret_cast<E*>(cm.nbr), cm.nnb, cmax, stream);
   return NNP_OK;
 }
 
@@ -515,6 +558,8 @@ TripArgs<P> trip_args(nnp_handle* h, Common& cm) {
   t.lcap = h->lcap;
   t.pos4 = cm.bin.pos4;
   t.nbr = reinterpret_cast<const typename Vec4<typename Types<P>::T>::type*>(cm.nbr);
+  t.idx = cm.idx;
+  t.roff = cm.roff;
   t.nnb = cm.nnb;
   t.st = cm.d_st;
   t.tab = reinterpret_cast<const DevTab<typename Types<P>::T>*>(h->d_tab);
@@ -582,6 +627,16 @@ bool use_store(const nnp_handle* h) {
   }
 }
 
+// Layout of the neighbour list for the next build: the handle's choice where
+// only wave-level passes with recomputed derivatives will read it, otherwise
+// the padded entries every pass reads.
+template <int P>
+int list_layout(const nnp_handle* h) {
+  if (h->list_layout == NNP_LIST_PADDED || h->parallelism == NNP_PAR_THREAD || h->has_wide) return NNP_LIST_PADDED;
+  if (h->deriv_mode == NNP_DERIV_STORED && P != P_BF16) return NNP_LIST_PADDED;
+  return h->list_layout;
+}
+
 template <int P>
 nnp_status jac_setup(nnp_handle* h, Common& cm, JacArgs<P>& j) {
   using T = typename Types<P>::T;
@@ -619,6 +674,7 @@ nnp_status fwd_remember(nnp_handle* h, const Common& cm, const IO* pos, const in
   h->fwd_boxes.clear();
   for (const auto& d : cm.B.st) h->fwd_boxes.insert(h->fwd_boxes.end(), d.L, d.L + 3);
   h->fwd_cap = h->cap;
+  h->fwd_layout = cm.layout;
   return NNP_OK;
 }
 
@@ -773,11 +829,20 @@ nnp_status forward(nnp_handle* h, int n_struct, const int64_t* offs, const void*
   mk.mark("bin_sort");
   FwdBufs<P> bufs;
   if ((st = fwd_buffers<P>(h, cm, n_struct, bufs))) return st;
+  int layout = list_layout<P>(h);
   for (int attempt = 0; attempt < 8; ++attempt) {
-    if ((st = build_neighbors<T>(h, cm, stream))) return st;
+    if ((st = build_neighbors<T>(h, cm, stream, layout))) return st;
     const int r = check_flags(h, stream, cm, &st);
     if (r < 0) return st;
     if (r > 0) continue;  // capacity grew: rebuild the neighbour list
+    if (layout != NNP_LIST_PADDED) {
+      bool flat = false;
+      if ((st = use_flat<P>(h, 0, 1, &flat))) return st;
+      if (flat) {  // the thread level reads padded entries only
+        layout = NNP_LIST_PADDED;
+        continue;
+      }
+    }
     mk.mark("neighbors");
     return evaluate<P>(h, cm, mk, bufs, n_struct, pos, types, energies_dev, energy_host, ei_v, f_v, stream, remember);
   }
@@ -902,18 +967,33 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
   // the weight gradient run.  Otherwise they are rebuilt first.
   bool ready = fwd_reusable<IO>(h, cm, pos, types, stream, &st);
   if (st) return st;
+  if (ready && h->fwd_layout != NNP_LIST_PADDED) {  // a thread-level product needs padded entries
+    bool flat = false;
+    if ((st = use_flat<P>(h, 2, 2, &flat))) return st;
+    ready = !flat;
+  }
   if (ready) {
-    if ((st = bind_neighbors<T>(h, cm))) return st;
+    if ((st = bind_neighbors<T>(h, cm, h->fwd_layout))) return st;
     mk.mark("reuse");
   } else {
     if ((st = prepare<IO>(h, cm, pos, types, stream))) return st;
     mk.mark("bin_sort");
   }
+  int layout = list_layout<P>(h);
   for (int attempt = 0; attempt < 8 && !ready; ++attempt) {
-    if ((st = build_neighbors<T>(h, cm, stream))) return st;
+    if ((st = build_neighbors<T>(h, cm, stream, layout))) return st;
     const int r = check_flags(h, stream, cm, &st);
     if (r < 0) return st;
     if (r > 0) continue;  // capacity grew: rebuild the neighbour list
+    if (layout != NNP_LIST_PADDED) {
+      bool f_sf = false, f_jvp = false;
+      if ((st = use_flat<P>(h, 0, 0, &f_sf))) return st;
+      if ((st = use_flat<P>(h, 2, 2, &f_jvp))) return st;
+      if (f_sf || f_jvp) {  // the thread level reads padded entries only
+        layout = NNP_LIST_PADDED;
+        continue;
+      }
+    }
     mk.mark("neighbors");
     const bool store = use_store<P>(h);
     if constexpr (P != P_BF16) {
@@ -1423,6 +1503,16 @@ nnp_status nnp_md_run(nnp_handle* h, int64_t n_atoms, void* pos, void* vel, void
     case NNP_FP32: return md_run<P_FP32>(h, n_atoms, pos, vel, forces, types, box, masses, dt_fs, n_steps, epot, ekin, s);
     default: return md_run<P_BF16>(h, n_atoms, pos, vel, forces, types, box, masses, dt_fs, n_steps, epot, ekin, s);
   }
+}
+
+nnp_status nnp_set_list_layout(nnp_handle* h, int layout) {
+  if (!h) return NNP_E_ARG;
+  Claim claim(h);
+  if (!claim.ok) return NNP_E_STATE;
+  if (layout != NNP_LIST_PADDED && layout != NNP_LIST_INDEX && layout != NNP_LIST_COMPACT)
+    return fail(h, NNP_E_ARG, "layout must be NNP_LIST_PADDED, NNP_LIST_INDEX or NNP_LIST_COMPACT");
+  h->list_layout = layout;
+  return NNP_OK;
 }
 
 nnp_status nnp_set_md_skin(nnp_handle* h, double skin) {

@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(256) k_neighbors(const double4* __restrict__ p
                                                    int n_struct, const int* __restrict__ start, int n_el,
                                                    int total_cells, double rc2, int cap, E* __restrict__ nbr,
                                                    int4* __restrict__ nnb, int* __restrict__ flags,
-                                                   int* __restrict__ cmax) {
+                                                   int* __restrict__ cmax, const int* __restrict__ roff) {
   __shared__ double4 sp[NB_TILE];
   __shared__ int seg_first[MAX_EL * 27];
   __shared__ int seg_off[MAX_EL * 27 + 1];
@@ -332,7 +332,8 @@ __global__ void __launch_bounds__(256) k_neighbors(const double4* __restrict__ p
         const int c = cidx[ci];
         const double4 p = cpos[ci];
         int tot = c_tot[ci];
-        E* row = nbr + (int64_t)c * cap;
+        // padded row (stride cap), compact row at roff[c], or none (counting pass: nbr null)
+        E* row = nbr ? nbr + (roff ? (int64_t)roff[c] : (int64_t)c * cap) : nullptr;
         for (int u0 = 0; u0 < tl; u0 += WAVE) {
           const int u = u0 + lane;
           bool pass = false;
@@ -353,7 +354,7 @@ __global__ void __launch_bounds__(256) k_neighbors(const double4* __restrict__ p
           }
           const unsigned long long msk = __builtin_amdgcn_ballot_w64(pass);
           const int rank = tot + lanes_below(msk);
-          const bool keep = pass && rank < cap;
+          const bool keep = pass && rank < cap && row;
           if (keep) row[rank] = make_entry_as<E>(dx, dy, dz, sidx);
           // an element block starting inside this step: passing candidates before it
           const int g0 = t0 + u0;
@@ -598,10 +599,11 @@ template void launch_bin_sort<float>(const BinArgs&, const float*, hipStream_t);
 template void launch_bin_sort<double>(const BinArgs&, const double*, hipStream_t);
 
 template <class E>
-void launch_neighbors_as(const BinArgs& a, double rc, int cap, E* nbr, int4* nnb, int* cmax, hipStream_t stream) {
+void launch_neighbors_as(const BinArgs& a, double rc, int cap, E* nbr, int4* nnb, int* cmax, hipStream_t stream,
+                         const int* roff = nullptr) {
   if (a.n == 0) return;
   hipLaunchKernelGGL(k_neighbors<E>, dim3((unsigned)a.total_cells), dim3(256), 0, stream, a.pos4, a.st, a.n_struct,
-                     a.start, a.n_el, a.total_cells, rc * rc, cap, nbr, nnb, a.flags, cmax);
+                     a.start, a.n_el, a.total_cells, rc * rc, cap, nbr, nnb, a.flags, cmax, roff);
   hipLaunchKernelGGL(k_max_count, dim3((unsigned)std::max(1, (a.total_cells + MAXC_PER - 1) / MAXC_PER)), dim3(256), 0,
                      stream, a.total_cells, cmax, a.flags);
 }
@@ -616,6 +618,39 @@ template void launch_neighbors<double>(const BinArgs&, double, int, double4*, in
 
 void launch_neighbor_index(const BinArgs& a, double rc, int cap, int* nbr, int4* nnb, int* cmax, hipStream_t stream) {
   launch_neighbors_as<int>(a, rc, cap, nbr, nnb, cmax, stream);
+}
+
+template <class T>
+void launch_neighbor_counts(const BinArgs& a, double rc, int4* nnb, int* cmax, hipStream_t stream) {
+  launch_neighbors_as<typename Vec4<T>::type>(a, rc, INT32_MAX, nullptr, nnb, cmax, stream);
+}
+template void launch_neighbor_counts<float>(const BinArgs&, double, int4*, int*, hipStream_t);
+template void launch_neighbor_counts<double>(const BinArgs&, double, int4*, int*, hipStream_t);
+
+template <class T>
+void launch_neighbors_compact(const BinArgs& a, double rc, const int* roff, typename Vec4<T>::type* nbr, int4* nnb,
+                              int* cmax, hipStream_t stream) {
+  launch_neighbors_as<typename Vec4<T>::type>(a, rc, INT32_MAX, nbr, nnb, cmax, stream, roff);
+}
+template void launch_neighbors_compact<float>(const BinArgs&, double, const int*, float4*, int4*, int*, hipStream_t);
+template void launch_neighbors_compact<double>(const BinArgs&, double, const int*, double4*, int4*, int*,
+                                               hipStream_t);
+
+__global__ void __launch_bounds__(256) k_row_lengths(int64_t n, const int4* __restrict__ nnb, int* __restrict__ len) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int4 v = nnb[c];
+  len[c] = v.x + v.y + v.z + v.w;
+}
+
+void launch_row_offsets(int64_t n, const int4* nnb, int* len, int* roff, int* tmp, int* partial, hipStream_t stream) {
+  if (n == 0) return;
+  const int ni = (int)n;
+  hipLaunchKernelGGL(k_row_lengths, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, nnb, len);
+  const int nb = (ni + SCAN_PER - 1) / SCAN_PER;
+  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(1024), 0, stream, ni, len, partial);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, stream, nb, ni, partial, roff);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, stream, ni, len, partial, roff, tmp);
 }
 
 template <class TIn>

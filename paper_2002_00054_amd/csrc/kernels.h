@@ -34,8 +34,18 @@ void launch_bin_sort(const BinArgs& a, const TIn* pos, hipStream_t stream);
 template <class T>
 void launch_neighbors(const BinArgs& a, double rc, int cap, typename Vec4<T>::type* nbr, int4* nnb, int* cmax,
                       hipStream_t stream);
-// Rows of neighbour indices alone (the Verlet-skin list of the MD driver).
+// Rows of neighbour indices alone (the Verlet-skin list of the MD driver and
+// the index-entry list layout).
 void launch_neighbor_index(const BinArgs& a, double rc, int cap, int* nbr, int4* nnb, int* cmax, hipStream_t stream);
+// Compact rows (no padding): a counting pass (nnb receives the exact counts),
+// the exclusive scan of the row lengths into roff[0..n] (int; the caller
+// checks the total fits), then the write pass into nbr at roff.
+template <class T>
+void launch_neighbor_counts(const BinArgs& a, double rc, int4* nnb, int* cmax, hipStream_t stream);
+void launch_row_offsets(int64_t n, const int4* nnb, int* len, int* roff, int* tmp, int* partial, hipStream_t stream);
+template <class T>
+void launch_neighbors_compact(const BinArgs& a, double rc, const int* roff, typename Vec4<T>::type* nbr, int4* nnb,
+                              int* cmax, hipStream_t stream);
 // Sorted positions from the caller's in the kept order; flags[0] bit 2 if any
 // atom moved more than lim from ref (its sorted position at the skin build).
 template <class TIn>
@@ -63,7 +73,9 @@ struct TripArgs {
   int cap;                   // neighbour slots per atom (row stride of nbr)
   int lcap;                  // LDS capacity: >= the most neighbours of any atom
   const double4* pos4;
-  const typename Vec4<T>::type* nbr;  // [n][cap] (dx, dy, dz, j) entries
+  const typename Vec4<T>::type* nbr;  // [n][cap] (dx, dy, dz, j) entries (null with idx)
+  const int* idx;            // or [n][cap] neighbour indices alone (wave-level passes only)
+  const int* roff;           // null: row c at c * cap; else compact rows at roff[c] (wave-level passes only)
   const int4* nnb;           // [n] neighbours per element block
   const DevStruct* st;
   const DevTab<T>* tab;
