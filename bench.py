@@ -207,15 +207,20 @@ def report(table, nets, sections=None):
         pot.close()
         del x, t
         torch.cuda.empty_cache()
-    # level of parallelism of the SF and force passes: a wave per centre against a thread per centre
-    for wl, bb, tb, nt in ((("ni", synth.fcc_box(72, 72), ni_table, ni_nets),
-                            ("water", synth.water_box(88, 22), table, nets)) if want("parallelism") else ()):
-        for mode in ("wave", "thread"):
+    # level of parallelism of the SF and force passes: a wave per centre, two waves per centre and a
+    # thread per centre, on both workloads at full size and on small water boxes (192 to 98,304
+    # atoms, where the number of centres, not the work per centre, limits a launch)
+    par_cases = ((("ni", synth.fcc_box(72, 72), ni_table, ni_nets, ("wave", "wave2", "thread")),
+                  ("water", synth.water_box(88, 22), table, nets, ("wave", "wave2", "thread")))
+                 + tuple(("water", synth.water_box(sd, 100 + sd), table, nets, ("wave", "wave2"))
+                         for sd in (4, 8, 16, 32))) if want("parallelism") else ()
+    for wl, bb, tb, nt, modes in par_cases:
+        for mode in modes:
             pot = Potential(tb, nt, precision="fp32", elements=("Ni",) if wl == "ni" else ("H", "O"))
             pot.set_parallelism(mode)
             x = torch.tensor(bb.pos, dtype=torch.float32, device=dev)
             t = torch.tensor(bb.types, dtype=torch.int32, device=dev)
-            ms, st = time_form(pot, x, t, bb.box, 5 if mode == "wave" else 3, 1)
+            ms, st = time_form(pot, x, t, bb.box, 3 if mode == "thread" else (5 if bb.n_atoms > 10 ** 6 else 20), 2)
             print(json.dumps({"report": "parallelism", "workload": wl, "form": "fp32", "level": mode,
                               "atoms": bb.n_atoms, "ms_per_step": ms, "stages_ms": st}), flush=True)
             pot.close()

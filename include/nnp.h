@@ -271,18 +271,27 @@ int64_t nnp_md_list_builds(const nnp_handle* h);
  *  NNP_PAR_THREAD  one thread per centre atom, walking its neighbours and
  *                  pairs alone (the paper's flat level); kept for comparison.
  *  NNP_PAR_AUTO    (default) the faster level; on this device that is a
- *                  wave per centre for long and short neighbour rows alike,
- *                  except for a batch whose densest atom has more neighbours
- *                  than the wave level can stage in LDS (160 KB per
- *                  workgroup of four waves: from about 310 neighbours in
- *                  the FP64 force-adjoint pass to about 730 in the FP32
- *                  force pass): that batch takes the thread level.
- * NNP_PAR_WAVE with such a batch is NNP_E_ARG, reported before any SF or
- * force kernel is launched.
+ *                  wave per centre for long and short neighbour rows alike.
+ *                  Two waves per centre are taken instead for a batch of at
+ *                  most 2,048 atoms (too few centres to fill the device
+ *                  otherwise) and for a batch whose densest atom has more
+ *                  neighbours than one wave per centre can stage in LDS
+ *                  (160 KB per workgroup of four centres: from about 310
+ *                  neighbours in the FP64 force-adjoint pass to about 730
+ *                  in the FP32 force pass; two waves per centre hold two
+ *                  centres per workgroup).  Beyond their LDS too, the batch
+ *                  takes the thread level.
+ *  NNP_PAR_WAVE2   two wavefronts per centre atom (the paper's third level,
+ *                  threads over atoms, neighbours and neighbour pairs): both
+ *                  share the centre's neighbour records and force sums in
+ *                  LDS; the first stages the neighbours, then the two split
+ *                  the walk over neighbour pairs and their SF sums are added.
+ * NNP_PAR_WAVE or NNP_PAR_WAVE2 with such a batch is NNP_E_ARG, reported
+ * before any SF or force kernel is launched.
  * Both give the same results up to rounding order; the force-adjoint pass of
  * nnp_backward follows the same choice.  An unknown mode is NNP_E_ARG.
  */
-typedef enum { NNP_PAR_AUTO = 0, NNP_PAR_WAVE = 1, NNP_PAR_THREAD = 2 } nnp_parallelism;
+typedef enum { NNP_PAR_AUTO = 0, NNP_PAR_WAVE = 1, NNP_PAR_THREAD = 2, NNP_PAR_WAVE2 = 3 } nnp_parallelism;
 nnp_status nnp_set_parallelism(nnp_handle* h, int mode);
 
 /*

@@ -560,6 +560,7 @@ TripArgs<P> trip_args(nnp_handle* h, Common& cm) {
   t.nbr = reinterpret_cast<const typename Vec4<typename Types<P>::T>::type*>(cm.nbr);
   t.idx = cm.idx;
   t.roff = cm.roff;
+  t.wpc = 1;  // set with the level (use_flat)
   t.nnb = cm.nnb;
   t.st = cm.d_st;
   t.tab = reinterpret_cast<const DevTab<typename Types<P>::T>*>(h->d_tab);
@@ -595,22 +596,43 @@ int check_flags(nnp_handle* h, hipStream_t stream, Common& cm, nnp_status* st) {
 }
 
 // Level of the pair passes of modes mode_a and mode_b (0 SF, 1 force, 2
-// force-adjoint product).  A thread per centre when asked for or when the
-// table holds wide angular SFs; otherwise a wave per centre (measured faster
-// on both workloads, short rows included), unless an atom has more
-// neighbours than the wave level can stage in LDS: then NNP_PAR_AUTO takes
-// the thread level, which reads the rows from HBM, and an explicit
-// NNP_PAR_WAVE is refused before any launch.
+// force-adjoint product): *flat for a thread per centre, else *wpc waves per
+// centre.  A thread per centre when asked for or when the table holds wide
+// angular SFs; the wave levels when asked for, refused before any launch if
+// an atom has more neighbours than they can stage in LDS.  NNP_PAR_AUTO
+// takes one wave per centre (measured the fastest on both workloads, short
+// rows included); for an atom beyond its LDS, two waves per centre (a
+// workgroup then holds two centres, not four), and beyond that the thread
+// level, which reads the rows from HBM.  Small batches take two waves per
+// centre under NNP_PAR_AUTO (AUTO_WAVE2_ATOMS).
+// Batches of at most this many atoms take two waves per centre under
+// NNP_PAR_AUTO: with fewer than 8 centres per CU the second wave of each
+// centre fills the machine (measured on water: 192 and 1,536 atoms 5-20 %
+// faster SF and force passes, 12,288 atoms 12 % slower).
+constexpr int64_t AUTO_WAVE2_ATOMS = 2048;
+
 template <int P>
-nnp_status use_flat(nnp_handle* h, int mode_a, int mode_b, bool* flat) {
+nnp_status use_flat(nnp_handle* h, int mode_a, int mode_b, bool* flat, int* wpc = nullptr, int64_t n_atoms = -1) {
+  int w = h->parallelism == NNP_PAR_WAVE2 ||
+                  (h->parallelism == NNP_PAR_AUTO && n_atoms >= 0 && n_atoms <= AUTO_WAVE2_ATOMS)
+              ? 2
+              : 1;
+  if (wpc) *wpc = w;
   *flat = h->parallelism == NNP_PAR_THREAD || h->has_wide;
   if (*flat) return NNP_OK;
-  const size_t lds =
-      std::max(triplet_lds_bytes<P>(mode_a, h->variant, h->lcap), triplet_lds_bytes<P>(mode_b, h->variant, h->lcap));
+  auto lds_of = [&](int k) {
+    return std::max(triplet_lds_bytes<P>(mode_a, h->variant, h->lcap, k),
+                    triplet_lds_bytes<P>(mode_b, h->variant, h->lcap, k));
+  };
+  const size_t lds = lds_of(w);
   if (lds <= lds_limit()) return NNP_OK;
-  if (h->parallelism == NNP_PAR_WAVE)
+  if (h->parallelism == NNP_PAR_WAVE || h->parallelism == NNP_PAR_WAVE2)
     return fail(h, NNP_E_ARG, "an atom with " + std::to_string(h->lcap) + " neighbours needs " + std::to_string(lds) +
                                   " bytes of LDS per workgroup at the wave level, more than the device allows");
+  if (lds_of(2) <= lds_limit()) {
+    if (wpc) *wpc = 2;
+    return NNP_OK;
+  }
   *flat = true;
   return NNP_OK;
 }
@@ -774,7 +796,7 @@ nnp_status evaluate(nnp_handle* h, Common& cm, Marks& mk, const FwdBufs<P>& b, i
   }
   if (!store) {
     bool flat = false;
-    if ((st = use_flat<P>(h, 0, 1, &flat))) return st;
+    if ((st = use_flat<P>(h, 0, 1, &flat, &ta.wpc, n))) return st;
     ta.G = b.G;
     if (flat) launch_flat<P>(0, ta, stream);
     else launch_triplet<P>(0, h->variant, ta, stream);
@@ -1008,7 +1030,7 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
     if (!store) {
       TripArgs<P> ta = trip_args<P>(h, cm);
       bool flat = false;
-      if ((st = use_flat<P>(h, 0, 0, &flat))) return st;
+      if ((st = use_flat<P>(h, 0, 0, &flat, &ta.wpc, n))) return st;
       ta.G = G;
       if (flat) launch_flat<P>(0, ta, stream);
       else launch_triplet<P>(0, h->variant, ta, stream);
@@ -1034,7 +1056,7 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
   if (!store) {
     TripArgs<P> ta = trip_args<P>(h, cm);
     bool flat = false;
-    if ((st = use_flat<P>(h, 2, 2, &flat))) return st;
+    if ((st = use_flat<P>(h, 2, 2, &flat, &ta.wpc, n))) return st;
     ta.delta = delta;
     ta.V = V;
     if (flat) launch_flat<P>(2, ta, stream);
@@ -1536,8 +1558,8 @@ nnp_status nnp_set_parallelism(nnp_handle* h, int mode) {
   if (!h) return NNP_E_ARG;
   Claim claim(h);
   if (!claim.ok) return NNP_E_STATE;
-  if (mode != NNP_PAR_AUTO && mode != NNP_PAR_WAVE && mode != NNP_PAR_THREAD)
-    return fail(h, NNP_E_ARG, "parallelism must be NNP_PAR_AUTO, NNP_PAR_WAVE or NNP_PAR_THREAD");
+  if (mode != NNP_PAR_AUTO && mode != NNP_PAR_WAVE && mode != NNP_PAR_THREAD && mode != NNP_PAR_WAVE2)
+    return fail(h, NNP_E_ARG, "parallelism must be NNP_PAR_AUTO, NNP_PAR_WAVE, NNP_PAR_THREAD or NNP_PAR_WAVE2");
   h->parallelism = mode;
   return NNP_OK;
 }

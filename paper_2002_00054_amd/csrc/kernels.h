@@ -76,6 +76,7 @@ struct TripArgs {
   const typename Vec4<T>::type* nbr;  // [n][cap] (dx, dy, dz, j) entries (null with idx)
   const int* idx;            // or [n][cap] neighbour indices alone (wave-level passes only)
   const int* roff;           // null: row c at c * cap; else compact rows at roff[c] (wave-level passes only)
+  int wpc;                   // waves per centre of the wave-level passes (1 or 2)
   const int4* nnb;           // [n] neighbours per element block
   const DevStruct* st;
   const DevTab<T>* tab;
@@ -92,7 +93,7 @@ void launch_triplet(int mode, int ne, const TripArgs<P>& a, hipStream_t stream);
 template <int P>
 void launch_flat(int mode, const TripArgs<P>& a, hipStream_t stream);
 template <int P>
-size_t triplet_lds_bytes(int mode, int ne, int lcap);
+size_t triplet_lds_bytes(int mode, int ne, int lcap, int wpc);
 
 // ------------------------------------------------- stored-Jacobian form
 // J holds, for every centre c and neighbour slot t (entry e = c * cap + t),

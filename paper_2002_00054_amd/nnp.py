@@ -31,7 +31,7 @@ EXPORTS = ("nnp_create", "nnp_compute", "nnp_compute_noalloc", "nnp_compute_batc
            "nnp_destroy", "nnp_last_error")
 DERIV_MODES = {"recompute": 0, "stored": 1}
 LIST_LAYOUTS = {"padded": 0, "index": 1, "compact": 2}
-PARALLELISM = {"auto": 0, "wave": 1, "thread": 2}
+PARALLELISM = {"auto": 0, "wave": 1, "thread": 2, "wave2": 3}
 
 
 class NNPError(RuntimeError):
@@ -182,7 +182,8 @@ class Potential:
         return int(self._L.nnp_n_params(self._h))
 
     def set_parallelism(self, mode: str):
-        """SF and force passes: "auto" (default), "wave" or "thread" per centre."""
+        """SF and force passes: "auto" (default), "wave", "wave2" (two waves)
+        or "thread" per centre."""
         self._check(self._L.nnp_set_parallelism(self._h, PARALLELISM[mode]))
 
     def set_list_layout(self, layout: str):

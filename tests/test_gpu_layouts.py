@@ -8,7 +8,7 @@ workloads: water (two elements, 6 A) from the 192-atom box (two cells per
 axis: the deduplicated stencil and minimum images) to 12,288 atoms, and the
 fcc metal (3.9 A).  The weight gradient (force-adjoint pass on the same
 list) matches the oracle per parameter tensor, and a batch too dense for
-the wave level falls back to padded rows at the thread level.
+one wave per centre runs the index layout with two.
 """
 import numpy as np
 import pytest
@@ -93,9 +93,10 @@ def test_layout_weight_gradient_matches_oracle(layout):
 
 
 def test_index_layout_dense_batch_falls_back():
-    """A ball of ~580 atoms all within rc of each other needs the thread
-    level under the default parallelism; with the index layout requested the
-    call rebuilds padded rows for it and still matches the oracle."""
+    """A ball of ~580 atoms all within rc of each other is beyond one wave
+    per centre; under the default parallelism it takes two, which read the
+    index layout as well, and matches the oracle.  Named explicitly, the
+    thread level rebuilds padded rows and matches too."""
     rng = np.random.default_rng(17)
     g = np.arange(-2.9, 2.9001, 0.56)
     pts = np.array([(x, y, z) for x in g for y in g for z in g])
@@ -106,6 +107,9 @@ def test_index_layout_dense_batch_falls_back():
     ref = oracle_water().compute(b.pos, b.types, b.box, use_cells=True)
     pot = make_potential("fp64")
     pot.set_list_layout("index")
+    e, ei, f = run(pot, b)
+    check_fp64(ei, f, ref["Ei"], ref["F"])
+    pot.set_parallelism("thread")
     e, ei, f = run(pot, b)
     check_fp64(ei, f, ref["Ei"], ref["F"])
     pot.close()

@@ -1,8 +1,8 @@
-"""Both levels of parallelism of the SF and force passes (nnp_set_parallelism)
+"""The levels of parallelism of the SF and force passes (nnp_set_parallelism)
 against the FP64 oracle, on both workloads: one thread per centre on the
 water boxes (86 neighbours) and on the fcc boxes (18 neighbours), one wave
-per centre (also the default) named explicitly on the fcc boxes, at the
-usual bars, and the two levels against each other."""
+per centre (also the default) named explicitly on the fcc boxes, two waves
+per centre on both, at the usual bars, and the levels against each other."""
 import numpy as np
 import pytest
 
@@ -33,8 +33,44 @@ def test_water_thread_per_centre(form, side, seed):
     pot.close()
 
 
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("side,seed", [(4, 1), (7, 3), (16, 11)])
+def test_water_two_waves_per_centre(form, side, seed):
+    b = synth.water_box(side, seed)
+    say("water wave2", form, b.n_atoms)
+    pot = make_potential(form)
+    pot.set_parallelism("wave2")
+    e, ei, f = run(pot, b)
+    ref = oracle_water().compute(oracle_input(b, form), b.types, b.box, use_cells=True)
+    if form == "fp64":
+        check_fp64(ei, f, ref["Ei"], ref["F"])
+    elif form == "fp32":
+        check_fp32(ei, f, ref["Ei"], ref["F"])
+    else:
+        assert float(np.sqrt(np.mean((f - ref["F"]) ** 2))) <= 5e-3
+    pot.close()
+
+
+def test_two_waves_weight_gradient_matches_oracle():
+    """The force-adjoint pass with two waves per centre (3-box training
+    batch, FP64, per tensor)."""
+    table, nets = water_potential()
+    teacher = oracle.Potential(table, synth.teacher_nets())
+    boxes = [synth.water_box(s, 40 + i) for i, s in enumerate((4, 5, 4))]
+    Ehat, Fhat = oracle.batch_energy_forces(teacher, boxes)
+    L_ref, g_ref = oracle.loss_and_grad(oracle.Potential(table, nets), boxes, Ehat, Fhat)
+    pot = make_potential("fp64")
+    pot.set_parallelism("wave2")
+    L, g = gpu_loss_and_grad(pot, boxes, Ehat, Fhat, synth.flat_params(nets))
+    rel = per_tensor_rel(g, g_ref, nets)
+    say("wave2 fp64 weight-gradient rel-L2 per tensor, max", rel.max())
+    assert L == pytest.approx(L_ref, rel=1e-10)
+    assert rel.max() < 1e-8
+    pot.close()
+
+
 @pytest.mark.parametrize("form", ["fp64", "fp32"])
-@pytest.mark.parametrize("mode", ["wave", "thread"])
+@pytest.mark.parametrize("mode", ["wave", "wave2", "thread"])
 def test_fcc_levels(form, mode):
     table, nets = synth.ni_table_scaled(), synth.ni_nets()
     b = synth.fcc_box(8, 2)
@@ -53,15 +89,17 @@ def test_levels_agree_fp64():
     table, nets = synth.ni_table_scaled(), synth.ni_nets()
     b = synth.fcc_box(20, 3)
     out = {}
-    for mode in ("wave", "thread"):
+    for mode in ("wave", "thread", "wave2"):
         pot = make_potential("fp64", table, nets)
         pot.set_parallelism(mode)
         out[mode] = run(pot, b)
         pot.close()
-    (e1, ei1, f1), (e2, ei2, f2) = out["wave"], out["thread"]
-    assert e2 == pytest.approx(e1, rel=1e-13)
-    assert np.max(np.abs(ei2 - ei1)) < 1e-12 * np.max(np.abs(ei1))
-    assert np.max(np.abs(f2 - f1)) < 1e-12 * np.max(np.abs(f1))
+    e1, ei1, f1 = out["wave"]
+    for other in ("thread", "wave2"):
+        e2, ei2, f2 = out[other]
+        assert e2 == pytest.approx(e1, rel=1e-13)
+        assert np.max(np.abs(ei2 - ei1)) < 1e-12 * np.max(np.abs(ei1))
+        assert np.max(np.abs(f2 - f1)) < 1e-12 * np.max(np.abs(f1))
 
 
 def test_bad_mode():
@@ -86,12 +124,14 @@ def _dense_ball():
 
 
 def test_dense_cluster_beyond_wave_lds():
-    """Atoms with more neighbours than the wave level can stage in LDS (about
-    580 per atom: over 190 KB per workgroup in FP64, above the 160 KB a
-    workgroup can have).  Under the default level the handle takes the
-    thread level, which reads the rows from HBM, and matches the oracle
-    (FP64), forward and weight gradient alike; an explicit request for the
-    wave level is refused with NNP_E_ARG before any launch."""
+    """Atoms with more neighbours than one wave per centre can stage in LDS
+    (about 580 per atom: over 190 KB per workgroup of four centres in FP64,
+    above the 160 KB a workgroup can have).  Under the default level the
+    handle takes two waves per centre (two centres per workgroup, about half
+    the LDS) and matches the oracle (FP64), forward and weight gradient
+    alike; an explicit request for one wave per centre is refused with
+    NNP_E_ARG before any launch, and two waves per centre named explicitly
+    match the oracle too."""
     from paper_2002_00054_amd.nnp import NNPError
 
     b = _dense_ball()
@@ -107,13 +147,18 @@ def test_dense_cluster_beyond_wave_lds():
     pot.set_parallelism("wave")
     with pytest.raises(NNPError, match="NNP_E_ARG.*LDS"):
         run(pot, b)
+    # two waves per centre put two centres, not four, in a workgroup: the
+    # ball fits its LDS
+    pot.set_parallelism("wave2")
+    e, ei, f = run(pot, b)
+    check_fp64(ei, f, ref["Ei"], ref["F"])
     pot.close()
 
 
 def test_dense_cluster_gradient_default_level():
     """The weight gradient of the dense ball under the default level (its
-    force-adjoint pass also falls back to the thread level) against the
-    oracle, FP64, 1e-8 per parameter tensor."""
+    force-adjoint pass also takes two waves per centre) against the oracle,
+    FP64, 1e-8 per parameter tensor."""
     b = _dense_ball()
     table, nets = water_potential()
     teacher = synth.teacher_nets()
