@@ -110,7 +110,9 @@ def report(table, nets, sections=None):
     each, velocity Verlet MD steps (throughput and energy drift), and the CPU
     oracle on one thread and on all threads.  `sections` (a set of the line
     names: peaks, sweep, training, ni, ni_g9, parallelism, forward_derivatives,
-    md, cpu_baseline) limits the report to those lines; None runs them all."""
+    md, cpu_baseline, cpu_oracle_full) limits the report to those lines; None
+    runs them all (cpu_oracle_full, the oracle on the whole 2M-atom box, takes
+    a few minutes of host time)."""
     import numpy as np
     import torch
 
@@ -266,6 +268,44 @@ def report(table, nets, sections=None):
         pot.close()
         del t
         torch.cuda.empty_cache()
+    if want("cpu_oracle_full"):
+        # The FP64 oracle once on the whole 2,044,416-atom box (all host threads), in 8 ranges of
+        # centres that each report as they finish; then every atom of the GPU forms against it.
+        sys.path.insert(0, os.path.join(ROOT, "oracle"))
+        import oracle
+
+        bb = synth.water_box(88, 22)
+        opot = oracle.Potential(table, nets)
+        F_ref = np.zeros((bb.n_atoms, 3))
+        cuts = np.linspace(0, bb.n_atoms, 9).astype(np.int64)
+        ei_parts, t_all = [], 0.0
+        for k in range(8):
+            t0 = time.perf_counter()
+            ei_parts.append(opot.compute_centres(bb.pos, bb.types, bb.box, int(cuts[k]), int(cuts[k + 1]), F_ref))
+            dt = time.perf_counter() - t0
+            t_all += dt
+            print(json.dumps({"report": "cpu_oracle_full_progress", "range": k + 1, "of": 8,
+                              "centres": int(cuts[k + 1] - cuts[k]), "s": dt}), flush=True)
+        Ei_ref = np.concatenate(ei_parts)
+        line = {"report": "cpu_oracle_full", "atoms": bb.n_atoms, "cores": oracle.max_threads(),
+                "cpu_model": cpu_model(), "seconds": t_all, "atom_steps_per_s": bb.n_atoms / t_all,
+                "E_oracle": float(np.sum(Ei_ref))}
+        for form in ("fp64", "fp32"):
+            pot = Potential(table, nets, precision=form)
+            x = torch.tensor(bb.pos, dtype=pot.dtype, device=dev)
+            t = torch.tensor(bb.types, dtype=torch.int32, device=dev)
+            e, ei, f = pot.compute(x, t, bb.box)
+            ei = ei.double().cpu().numpy()
+            f = f.double().cpu().numpy()
+            line[form] = {"max_abs_dEi": float(np.max(np.abs(ei - Ei_ref))),
+                          "max_abs_dF": float(np.max(np.abs(f - F_ref))),
+                          "rel_dE": float(abs(e - line["E_oracle"]) / abs(line["E_oracle"]))}
+            pot.close()
+            del x, t
+            torch.cuda.empty_cache()
+        line["note"] = ("FP32 positions are float32-rounded on the GPU only, so the FP32 differences include "
+                        "that rounding; the FP64 ones are the parity of the whole box")
+        print(json.dumps(line), flush=True)
     for nt in ((0, 1) if want("cpu_baseline") else ()):  # all threads first: a thread count set once stays set
         cb = cpu_baseline(table, nets, budget_s=30.0 if nt == 1 else 12.0, nthreads=nt)
         print(json.dumps({"report": "cpu_baseline", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
@@ -288,7 +328,7 @@ def main():
                     help="print only the peaks / size-sweep / training / CPU report lines")
     ap.add_argument("--sections", default=None,
                     help="with --report: comma list of report lines to run (peaks, sweep, training, ni, ni_g9, "
-                         "parallelism, forward_derivatives, md, cpu_baseline); default all")
+                         "parallelism, forward_derivatives, md, cpu_baseline, cpu_oracle_full); default all")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB with a plain device copy (for HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -315,7 +355,7 @@ def main():
     table, nets = synth.water_table_scaled(), synth.water_nets()
     if args.report:
         known = {"peaks", "sweep", "training", "ni", "ni_g9", "parallelism", "forward_derivatives", "md",
-                 "cpu_baseline"}
+                 "cpu_baseline", "cpu_oracle_full"}
         sections = None if args.sections is None else {x for x in args.sections.split(",") if x}
         if sections is not None and not sections <= known:
             ap.error(f"unknown report sections {sorted(sections - known)}; known: {sorted(known)}")

@@ -10,6 +10,9 @@
  * enqueues work on `stream` (a hipStream_t; NULL = the null stream) and returns
  * at once; the caller times the launch with events on the same stream.
  *
+ * MFMA datasheet peaks (dense): FP32 157.3 TFLOP/s, FP64 78.6 TFLOP/s, BF16
+ * 2.5 PFLOP/s.
+ *
  * Return value: 0 on success, -1 for a bad argument (nothing launched), -4 if
  * the launch itself failed (hipGetLastError after the launch).
  */
@@ -35,6 +38,21 @@ int nnp_peak_fma_f64(double* out, int blocks, int iters, void* stream);
 /* FP32 base-2 exponential issue rate (v_exp_f32): 16 independent chains of
  * x <- 2^(-x), i.e. 16 * iters * 256 * blocks exponentials.  Same limits. */
 int nnp_peak_exp_f32(float* out, int blocks, int iters, void* stream);
+
+/* Matrix-core (MFMA) issue rates, the ceiling of the network kernel: each
+ * wave of the `blocks` workgroups (4 waves of 64 lanes each) runs `iters`
+ * rounds of 4 independent accumulator chains of one instruction shape:
+ *  nnp_peak_mfma_f32   v_mfma_f32_16x16x4f32, 2048 operations each
+ *                      (out: blocks * 256 floats);
+ *  nnp_peak_mfma_f64   v_mfma_f64_16x16x4f64, 2048 operations each
+ *                      (out: blocks * 256 doubles);
+ *  nnp_peak_mfma_bf16  v_mfma_f32_16x16x32_bf16, 16384 operations each
+ *                      (out: blocks * 256 floats).
+ * i.e. 4 * 4 * iters * blocks instructions.  `out` is written only to keep
+ * the chains live.  Same limits as the FMA probes. */
+int nnp_peak_mfma_f32(float* out, int blocks, int iters, void* stream);
+int nnp_peak_mfma_f64(double* out, int blocks, int iters, void* stream);
+int nnp_peak_mfma_bf16(float* out, int blocks, int iters, void* stream);
 
 /* Streaming device copy of `bytes` bytes (a multiple of 16; both pointers
  * 16-byte aligned, not overlapping): 2 * bytes of HBM traffic.  Launches a

@@ -514,6 +514,57 @@ int oracle_compute(const opot* p, int64_t N, const double* pos, const int* types
   return 0;
 }
 
+// The same evaluation restricted to the centres [lo, hi): their atomic
+// energies go to Ei[0 .. hi-lo), and the force terms they contribute,
+// -dE_i/dG_is dG_is/dr_m for every atom m, are ADDED to F (3 N values, set
+// by the caller).  Summed over centre ranges that cover every atom, this is
+// oracle_compute (forces are a sum over centres, Fig. 1(b) step 3); it lets a
+// large box be evaluated in parts that each finish.  Neighbours come from the
+// cell list of the whole box.
+int oracle_compute_centres(const opot* p, int64_t N, const double* pos, const int* types, const double* box,
+                           int64_t lo, int64_t hi, double* Ei, double* F, int nthreads) {
+  if (lo < 0 || hi > N || lo > hi) return -1;
+  set_threads(nthreads);
+  Pot P = parse(p);
+  const int ms = max_sf(P);
+  Cells C = build_cells(N, pos, box, P.rc_max);
+  const int64_t n = hi - lo;
+  std::vector<std::vector<int64_t>> nb(n);
+  std::vector<double> G((size_t)n * ms, 0.0), Cc((size_t)n * ms, 0.0);
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t q = 0; q < n; ++q) {
+    neighbours_of(C, lo + q, pos, box, P.rc_max, nb[q]);
+    descriptors(P, lo + q, nb[q], pos, types, box, &G[q * ms]);
+    Ei[q] = network(P, types[lo + q], &G[q * ms], &Cc[q * ms]);
+  }
+  int nt = 1;
+#ifdef _OPENMP
+  nt = omp_get_max_threads();
+#endif
+  std::vector<std::vector<double>> Fb(nt, std::vector<double>((size_t)3 * N, 0.0));
+#pragma omp parallel
+  {
+    int t = 0;
+#ifdef _OPENMP
+    t = omp_get_thread_num();
+#endif
+    std::vector<double>& fb = Fb[t];
+#pragma omp for schedule(dynamic, 8)
+    for (int64_t q = 0; q < n; ++q) {
+      const double* c = &Cc[q * ms];
+      descriptor_gradients(P, lo + q, nb[q], pos, types, box, [&](int64_t m, const double g[3], int s) {
+        for (int a = 0; a < 3; ++a) fb[3 * m + a] -= c[s] * g[a];
+      });
+    }
+  }
+  for (int64_t k = 0; k < 3 * N; ++k) {
+    double s = 0.0;
+    for (int t = 0; t < nt; ++t) s += Fb[t][k];
+    F[k] += s;
+  }
+  return 0;
+}
+
 // Descriptor-Jacobian-vector product v[i][s] = sum_m delta_m . dG_is/dr_m
 // (raw G), for the force term of the training-loss gradient.
 int oracle_sf_jvp(const opot* p, int64_t N, const double* pos, const int* types, const double* box,

@@ -76,6 +76,8 @@ def lib():
         L.oracle_sf_jvp.argtypes = [C.POINTER(_OPot), C.c_int64, dp, ip, dp, dp, dp, C.c_int, C.c_int, C.c_int]
         L.oracle_sampled.argtypes = [C.POINTER(_OPot), C.c_int64, dp, ip, dp, C.c_int64,
                                      C.POINTER(C.c_int64), dp, dp, C.c_int]
+        L.oracle_compute_centres.argtypes = [C.POINTER(_OPot), C.c_int64, dp, ip, dp, C.c_int64, C.c_int64, dp, dp,
+                                             C.c_int]
         L.oracle_max_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -174,6 +176,17 @@ class Potential:
                                  self.max_sf, int(use_cells), nthreads)
         assert rc == 0
         return v
+
+    def compute_centres(self, pos, types, box, lo, hi, F, nthreads=0):
+        """E_i of the centres [lo, hi) (returned) and their force terms added
+        into F (n x 3, float64, set by the caller); cell list, any box size."""
+        pos, types, box = self._inputs(pos, types, box)
+        assert F.dtype == np.float64 and F.flags.c_contiguous and F.shape == (pos.shape[0], 3)
+        Ei = np.zeros(hi - lo)
+        rc = lib().oracle_compute_centres(C.byref(self._s), pos.shape[0], _dp(pos), _ip(types), _dp(box),
+                                          int(lo), int(hi), _dp(Ei), _dp(F), nthreads)
+        assert rc == 0
+        return Ei
 
     def sampled(self, pos, types, box, idx, nthreads=0):
         """E_i and F_i of the atoms ``idx`` only (cell list; any box size)."""

@@ -1,5 +1,6 @@
 // Peak probes (libnnp_peaks.so): FP32/FP64 fused multiply-add and FP32
-// exponential issue rates, and a streaming HBM copy.  Built with the same
+// exponential issue rates, FP32/FP64/BF16 matrix-core (MFMA) rates, and a
+// streaming HBM copy.  Built with the same
 // flags as the energy+force kernels, so the FP32 probe issues single
 // v_fma_f32 instructions exactly as those kernels do.
 #include <hip/hip_runtime.h>
@@ -49,6 +50,35 @@ __global__ __launch_bounds__(LANES) void k_exp(float* out, int iters) {
 }
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// Matrix-core issue rates: every wave runs `iters` rounds of MCH independent
+// accumulator chains of one 16x16 MFMA shape (the shapes the network kernel
+// uses): 16x16x4 FP32 and FP64 (2 * 16 * 16 * 4 = 2048 operations each) and
+// 16x16x32 BF16 with FP32 accumulation (16384 operations).
+constexpr int MCH = 4;
+
+__device__ inline v4f mfma_step(float a, float b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ inline v4d mfma_step(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline v4f mfma_step(v8bf a, v8bf b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+
+template <class In, class Acc, class Out>
+__global__ __launch_bounds__(LANES) void k_mfma(Out* out, int iters, In a, In b) {
+  Acc acc[MCH];
+#pragma unroll
+  for (int c = 0; c < MCH; ++c) acc[c] = Acc{} + (Out)((threadIdx.x + c) & 7);
+#pragma unroll 2
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int c = 0; c < MCH; ++c) acc[c] = mfma_step(a, b, acc[c]);
+  }
+  Out s = 0;
+#pragma unroll
+  for (int c = 0; c < MCH; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  // never true (the sums stay positive): the store only keeps the chains live
+  if (s == (Out)-1) out[(int64_t)blockIdx.x * LANES + threadIdx.x] = s;
+}
 
 // Four independent 16-byte loads in flight per lane before the stores.
 __global__ __launch_bounds__(LANES) void k_copy(const v4f* __restrict__ src, v4f* __restrict__ dst, int64_t n) {
@@ -90,6 +120,29 @@ extern "C" int nnp_peak_fma_f64(double* out, int blocks, int iters, void* stream
 extern "C" int nnp_peak_exp_f32(float* out, int blocks, int iters, void* stream) {
   if (bad_shape(out, blocks, iters)) return -1;
   k_exp<<<blocks, LANES, 0, (hipStream_t)stream>>>(out, iters);
+  return launched();
+}
+
+extern "C" int nnp_peak_mfma_f32(float* out, int blocks, int iters, void* stream) {
+  if (bad_shape(out, blocks, iters)) return -1;
+  k_mfma<float, v4f, float><<<blocks, LANES, 0, (hipStream_t)stream>>>(out, iters, 0.5f, 1e-4f);
+  return launched();
+}
+
+extern "C" int nnp_peak_mfma_f64(double* out, int blocks, int iters, void* stream) {
+  if (bad_shape(out, blocks, iters)) return -1;
+  k_mfma<double, v4d, double><<<blocks, LANES, 0, (hipStream_t)stream>>>(out, iters, 0.5, 1e-4);
+  return launched();
+}
+
+extern "C" int nnp_peak_mfma_bf16(float* out, int blocks, int iters, void* stream) {
+  if (bad_shape(out, blocks, iters)) return -1;
+  v8bf a, b;
+  for (int k = 0; k < 8; ++k) {
+    a[k] = (__bf16)0.5f;
+    b[k] = (__bf16)1e-4f;
+  }
+  k_mfma<v8bf, v4f, float><<<blocks, LANES, 0, (hipStream_t)stream>>>(out, iters, a, b);
   return launched();
 }
 

@@ -1,5 +1,6 @@
 """Measured device peaks (libnnp_peaks.so): the attainable FP32 and FP64 FMA
-rates, the FP32 exponential rate and the streaming HBM copy bandwidth.
+rates, the FP32 exponential rate, the FP32/FP64/BF16 matrix-core rates and
+the streaming HBM copy bandwidth.
 
 Each probe is launched on torch's current stream and timed with events on
 that stream; the best of a few repetitions is kept.
@@ -11,7 +12,8 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnnp_peaks.so")
-EXPORTS = ("nnp_peak_fma_f32", "nnp_peak_fma_f64", "nnp_peak_exp_f32", "nnp_peak_copy")
+EXPORTS = ("nnp_peak_fma_f32", "nnp_peak_fma_f64", "nnp_peak_exp_f32", "nnp_peak_mfma_f32", "nnp_peak_mfma_f64",
+           "nnp_peak_mfma_bf16", "nnp_peak_copy")
 
 _lib = None
 
@@ -23,7 +25,8 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_2002_00054_amd.build")
     L = C.CDLL(path)
-    for name in ("nnp_peak_fma_f32", "nnp_peak_fma_f64", "nnp_peak_exp_f32"):
+    for name in ("nnp_peak_fma_f32", "nnp_peak_fma_f64", "nnp_peak_exp_f32", "nnp_peak_mfma_f32",
+                 "nnp_peak_mfma_f64", "nnp_peak_mfma_bf16"):
         f = getattr(L, name)
         f.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
         f.restype = C.c_int
@@ -70,6 +73,14 @@ def measure(reps: int = 5, copy_mib: int = 4096) -> dict:
             ("nnp_peak_exp_f32", L.nnp_peak_exp_f32, 16, "fp32_exp_tops")):
         ms = _best_ms(lambda: check(fn(C.c_void_p(out.data_ptr()), blocks, iters, stream), name), reps)
         res[key] = ops_per_iter * iters * 256 * blocks / (ms * 1e-3) / 1e12
+    # matrix cores: 4 waves per workgroup x 4 chains x operations per instruction
+    m_iters = 1 << 12
+    for name, fn, ops, key in (
+            ("nnp_peak_mfma_f32", L.nnp_peak_mfma_f32, 2048, "mfma_fp32_tflops"),
+            ("nnp_peak_mfma_f64", L.nnp_peak_mfma_f64, 2048, "mfma_fp64_tflops"),
+            ("nnp_peak_mfma_bf16", L.nnp_peak_mfma_bf16, 16384, "mfma_bf16_tflops")):
+        ms = _best_ms(lambda: check(fn(C.c_void_p(out.data_ptr()), blocks, m_iters, stream), name), reps)
+        res[key] = 4 * 4 * ops * m_iters * blocks / (ms * 1e-3) / 1e12
     nbytes = copy_mib << 20
     src = torch.rand(nbytes // 4, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)

@@ -56,6 +56,9 @@ def test_peaks_reject_bad_arguments():
     assert L.nnp_peak_fma_f32(None, 1, 1, None) == -1
     assert L.nnp_peak_fma_f64(C.c_void_p(16), 0, 1, None) == -1
     assert L.nnp_peak_exp_f32(C.c_void_p(16), 1, 0, None) == -1
+    assert L.nnp_peak_mfma_f32(None, 1, 1, None) == -1
+    assert L.nnp_peak_mfma_f64(C.c_void_p(16), 0, 1, None) == -1
+    assert L.nnp_peak_mfma_bf16(C.c_void_p(16), 1, 1 << 25, None) == -1
     assert L.nnp_peak_copy(C.c_void_p(16), C.c_void_p(32), 32, 1, None) == -1  # overlapping
     assert L.nnp_peak_copy(C.c_void_p(16), C.c_void_p(4096), 8, 1, None) == -1  # not a multiple of 16
 

@@ -355,6 +355,22 @@ def test_sampled_matches_full():
     np.testing.assert_allclose(F, full["F"][idx], rtol=1e-10, atol=1e-11)
 
 
+def test_centre_ranges_sum_to_full():
+    """The centre-range evaluator (for timing a box too big for one silent
+    run) over uneven ranges covering every atom equals the full one: the
+    energies per centre, and the forces as the sum of the ranges' terms.  An
+    empty range adds nothing, and the summed forces still cancel."""
+    pot = oracle_water()
+    b = synth.water_box(6, 5)
+    full = pot.compute(b.pos, b.types, b.box)
+    F = np.zeros((b.n_atoms, 3))
+    cuts = [0, 1, 200, 200, 513, b.n_atoms]
+    Ei = np.concatenate([pot.compute_centres(b.pos, b.types, b.box, lo, hi, F) for lo, hi in zip(cuts, cuts[1:])])
+    np.testing.assert_allclose(Ei, full["Ei"], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(F, full["F"], rtol=1e-10, atol=1e-11)
+    assert np.max(np.abs(F.sum(axis=0))) < 1e-9
+
+
 # -------------------------------------------------- P10 loss gradient
 @pytest.mark.slow
 def test_loss_gradient_matches_finite_differences():
