@@ -299,17 +299,17 @@ __global__ void __launch_bounds__(FLAT) k_flat_force(TripArgs<P> a) {
         else pairs(std::false_type{});
       }
       const int64_t jj = entry_index(A);
-      atomic_add(&a.F[3 * jj + 0], (FAcc)(-gx));
-      atomic_add(&a.F[3 * jj + 1], (FAcc)(-gy));
-      atomic_add(&a.F[3 * jj + 2], (FAcc)(-gz));
+      atomic_add(&a.F[jj], (FAcc)(-gx));
+      atomic_add(&a.F[a.n + jj], (FAcc)(-gy));
+      atomic_add(&a.F[2 * a.n + jj], (FAcc)(-gz));
       fix += gx;
       fiy += gy;
       fiz += gz;
     }
   }
-  atomic_add(&a.F[3 * c + 0], (FAcc)fix);
-  atomic_add(&a.F[3 * c + 1], (FAcc)fiy);
-  atomic_add(&a.F[3 * c + 2], (FAcc)fiz);
+  atomic_add(&a.F[c], (FAcc)fix);
+  atomic_add(&a.F[a.n + c], (FAcc)fiy);
+  atomic_add(&a.F[2 * a.n + c], (FAcc)fiz);
 }
 
 // Force-adjoint product of the differentiation form, one thread per centre:

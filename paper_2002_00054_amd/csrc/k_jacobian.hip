@@ -335,9 +335,9 @@ __global__ void __launch_bounds__(256) k_jac_force(JacArgs<P> a) {
       f2 += cs * js[2 * plane];
     }
     const int64_t j = entry_index(a.nbr[e]);
-    atomic_add(&a.F[3 * j + 0], (FAcc)(-f0));
-    atomic_add(&a.F[3 * j + 1], (FAcc)(-f1));
-    atomic_add(&a.F[3 * j + 2], (FAcc)(-f2));
+    atomic_add(&a.F[j], (FAcc)(-f0));
+    atomic_add(&a.F[a.n + j], (FAcc)(-f1));
+    atomic_add(&a.F[2 * a.n + j], (FAcc)(-f2));
     fi0 += f0;
     fi1 += f1;
     fi2 += f2;
@@ -346,9 +346,9 @@ __global__ void __launch_bounds__(256) k_jac_force(JacArgs<P> a) {
   fi1 = wave_sum(fi1);
   fi2 = wave_sum(fi2);
   if (lane == 0) {
-    atomic_add(&a.F[3 * c + 0], (FAcc)fi0);
-    atomic_add(&a.F[3 * c + 1], (FAcc)fi1);
-    atomic_add(&a.F[3 * c + 2], (FAcc)fi2);
+    atomic_add(&a.F[c], (FAcc)fi0);
+    atomic_add(&a.F[a.n + c], (FAcc)fi1);
+    atomic_add(&a.F[2 * a.n + c], (FAcc)fi2);
   }
 }
 

@@ -32,9 +32,9 @@ __global__ void __launch_bounds__(256) k_unpermute(int64_t n, const int* __restr
   Ei_o[i] = (double)e;
   if (Ei_out) Ei_out[i] = e;
   if (F_out) {
-    F_out[3 * i + 0] = (IO)F_s[3 * s + 0];
-    F_out[3 * i + 1] = (IO)F_s[3 * s + 1];
-    F_out[3 * i + 2] = (IO)F_s[3 * s + 2];
+    F_out[3 * i + 0] = (IO)F_s[s];  // sorted accumulator: component planes [3][n]
+    F_out[3 * i + 1] = (IO)F_s[n + s];
+    F_out[3 * i + 2] = (IO)F_s[2 * n + s];
   }
 }
 

@@ -82,7 +82,7 @@ struct TripArgs {
   const DevTab<T>* tab;
   IO* G;                     // SF: G~ rows [n][LD]
   const IO* C;               // FORCE: dE/dG rows [n][LD]
-  FAcc* F;                   // FORCE: force accumulator [n][3] (sorted)
+  FAcc* F;                   // FORCE: force accumulator [3][n] (component planes, sorted order)
   const IO* delta;           // JVP: dL/dF [n][3] (sorted)
   IO* V;                     // JVP: rows [n][LD]
 };
@@ -116,7 +116,7 @@ struct JacArgs {
   T* J;                      // [3 * max n_sf][plane]
   IO* G;                     // SF pass: G~ rows [n][LD]
   const IO* C;               // force contraction: dE/dG rows [n][LD]
-  FAcc* F;                   // force contraction: accumulator [n][3] (sorted)
+  FAcc* F;                   // force contraction: accumulator [3][n] (component planes, sorted order)
   const IO* delta;           // JVP contraction: dL/dF [n][3] (sorted)
   IO* V;                     // JVP contraction: rows [n][LD]
 };
