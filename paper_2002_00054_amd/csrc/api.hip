@@ -99,6 +99,7 @@ struct nnp_handle {
   // MD driver: Verlet skin (A; 0 = rebuild the list at every step), the skin
   // list's state and capacity, and the neighbour-list builds of the last run
   int list_layout = NNP_LIST_PADDED;     // of the wave-level passes with recomputed derivatives
+  int pair_masks = 1;                    // SF pass records its pair tests for the force pass
   size_t compact_entries = 0;            // entries of the last compact list
   int fwd_layout = NNP_LIST_PADDED;      // layout of the list the last batch forward left
   double md_skin = 0.0;
@@ -610,6 +611,9 @@ int check_flags(nnp_handle* h, hipStream_t stream, Common& cm, nnp_status* st) {
 // centre fills the machine (measured on water: 192 and 1,536 atoms 5-20 %
 // faster SF and force passes, 12,288 atoms 12 % slower).
 constexpr int64_t AUTO_WAVE2_ATOMS = 2048;
+// Largest pair-mask buffer (n atoms x pair_step_bound(lcap) steps, 8 bytes each);
+// beyond it the force pass tests the pairs itself.
+constexpr size_t PAIR_MASK_MAX_BYTES = (size_t)16 << 30;
 
 template <int P>
 nnp_status use_flat(nnp_handle* h, int mode_a, int mode_b, bool* flat, int* wpc = nullptr, int64_t n_atoms = -1) {
@@ -797,6 +801,15 @@ nnp_status evaluate(nnp_handle* h, Common& cm, Marks& mk, const FwdBufs<P>& b, i
   if (!store) {
     bool flat = false;
     if ((st = use_flat<P>(h, 0, 1, &flat, &ta.wpc, n))) return st;
+    if (!flat && ta.wpc == 1 && h->pair_masks && !h->arena_on) {
+      // one bit per candidate pair, written by the SF pass for the force pass
+      const int blocks = (pair_step_bound(h->lcap, h->n_el) + 31) / 32;
+      const size_t words = (size_t)n * blocks * WAVE;
+      if (words * sizeof(unsigned) <= PAIR_MASK_MAX_BYTES) {
+        if ((st = ensure_t(h, "pair_masks", words, &ta.pm))) return st;
+        ta.pm_stride = blocks;
+      }
+    }
     ta.G = b.G;
     if (flat) launch_flat<P>(0, ta, stream);
     else launch_triplet<P>(0, h->variant, ta, stream);
@@ -1534,6 +1547,15 @@ nnp_status nnp_set_list_layout(nnp_handle* h, int layout) {
   if (layout != NNP_LIST_PADDED && layout != NNP_LIST_INDEX && layout != NNP_LIST_COMPACT)
     return fail(h, NNP_E_ARG, "layout must be NNP_LIST_PADDED, NNP_LIST_INDEX or NNP_LIST_COMPACT");
   h->list_layout = layout;
+  return NNP_OK;
+}
+
+nnp_status nnp_set_pair_masks(nnp_handle* h, int on) {
+  if (!h) return NNP_E_ARG;
+  Claim claim(h);
+  if (!claim.ok) return NNP_E_STATE;
+  if (on != 0 && on != 1) return fail(h, NNP_E_ARG, "on must be 0 or 1");
+  h->pair_masks = on;
   return NNP_OK;
 }
 

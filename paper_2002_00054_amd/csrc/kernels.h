@@ -85,7 +85,24 @@ struct TripArgs {
   FAcc* F;                   // FORCE: force accumulator [3][n] (component planes, sorted order)
   const IO* delta;           // JVP: dL/dF [n][3] (sorted)
   IO* V;                     // JVP: rows [n][LD]
+  // Pair-test masks of the one-wave pair walk (wpc 1): the SF pass writes the
+  // test of lane l at step s of centre c to bit s % 32 of
+  // pm[(c * pm_stride + s / 32) * 64 + l], the force pass reads them instead
+  // of repeating the r_jk < rc test.  pm_stride = 0: both passes test the
+  // pairs.  pm_stride >= ceil(pair_step_bound(lcap, n_el) / 32).
+  unsigned* pm;
+  int pm_stride;
 };
+
+// Most steps the one-wave pair walk can take for a centre with m neighbours
+// of n_el elements.  A chunk of mJ <= 64 lanes walks a range of D deltas in
+// ceil(D / R) steps with R = 1 (mJ > 32) or floor(64 / mJ) (R mJ > 32), so
+// at most 2 mJ D / 64 + 1 steps; D = mB across elements and <= mA / 2 within
+// one, and summed over the classes the mJ D terms give at most m^2 / 2.  The
+// chunks number at most sum over classes of (mA / 64 + 1).
+__host__ __device__ constexpr int pair_step_bound(int m, int n_el) {
+  return (m * m + n_el * m + 63) / 64 + n_el * (n_el + 1) / 2;
+}
 
 template <int P>
 void launch_triplet(int mode, int ne, const TripArgs<P>& a, hipStream_t stream);

@@ -25,7 +25,7 @@ EXPORTS = ("nnp_create", "nnp_compute", "nnp_compute_noalloc", "nnp_compute_batc
            "nnp_set_params",
            "nnp_get_params", "nnp_set_profiling", "nnp_last_timings", "nnp_neighbor_capacity",
            "nnp_set_neighbor_capacity", "nnp_count_work", "nnp_md_run", "nnp_set_md_skin", "nnp_md_list_builds",
-           "nnp_set_parallelism", "nnp_set_list_layout",
+           "nnp_set_parallelism", "nnp_set_list_layout", "nnp_set_pair_masks",
            "nnp_set_derivative_mode",
            "nnp_workspace_bytes",
            "nnp_destroy", "nnp_last_error")
@@ -85,6 +85,7 @@ def load_library(path: str = LIB_PATH):
     L.nnp_count_work.argtypes = [vp, i64, vp, vp, dp, C.POINTER(i64), vp]
     L.nnp_md_run.argtypes = [vp, i64, vp, vp, vp, vp, dp, dp, C.c_double, C.c_int, dp, dp, vp]
     L.nnp_set_list_layout.argtypes = [vp, C.c_int]
+    L.nnp_set_pair_masks.argtypes = [vp, C.c_int]
     L.nnp_set_md_skin.argtypes = [vp, C.c_double]
     L.nnp_md_list_builds.argtypes = [vp]
     L.nnp_md_list_builds.restype = i64
@@ -100,7 +101,7 @@ def load_library(path: str = LIB_PATH):
                  "nnp_set_params",
                  "nnp_get_params", "nnp_set_profiling", "nnp_set_neighbor_capacity", "nnp_last_timings",
                  "nnp_neighbor_capacity", "nnp_count_work", "nnp_md_run", "nnp_set_md_skin", "nnp_set_parallelism",
-                 "nnp_set_list_layout",
+                 "nnp_set_list_layout", "nnp_set_pair_masks",
                  "nnp_set_derivative_mode"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -190,6 +191,11 @@ class Potential:
         """Neighbour list of the wave-level passes: "padded" (default),
         "index" (4-byte indices, positions gathered) or "compact" (no padding)."""
         self._check(self._L.nnp_set_list_layout(self._h, LIST_LAYOUTS[layout]))
+
+    def set_pair_masks(self, on: bool):
+        """Whether the SF pass records its pair tests for the force pass
+        (default on; results are the same)."""
+        self._check(self._L.nnp_set_pair_masks(self._h, 1 if on else 0))
 
     def set_derivative_mode(self, mode: str):
         """"recompute" (default) or "stored" (keep dG/dr per neighbour slot)."""
