@@ -202,6 +202,8 @@ __device__ inline int lanes_below(unsigned long long m) {
 __device__ inline double exp_scaled(double x_ln, double /*x_log2*/) { return exp(x_ln); }
 __device__ inline float exp_scaled(float /*x_ln*/, float x_log2) { return __builtin_amdgcn_exp2f(x_log2); }
 
+__device__ inline float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ inline double rsqrt_t(double s) { return 1.0 / sqrt(s); }
 __device__ inline float rsqrt_t(float s) { return __builtin_amdgcn_rsqf(s); }
 
