@@ -109,8 +109,8 @@ def report(table, nets, sections=None):
     targets) with recomputed and with stored SF derivatives, the forward with
     each, velocity Verlet MD steps (throughput and energy drift), and the CPU
     oracle on one thread and on all threads.  `sections` (a set of the line
-    names: peaks, sweep, training, ni, ni_g9, parallelism, forward_derivatives,
-    md, cpu_baseline, cpu_oracle_full) limits the report to those lines; None
+    names: peaks, sweep, training, ni, ni_g9, parallelism, layouts, pair_masks,
+    forward_derivatives, md, cpu_baseline, cpu_oracle_full) limits the report to those lines; None
     runs them all (cpu_oracle_full, the oracle on the whole 2M-atom box, takes
     a few minutes of host time)."""
     import numpy as np
@@ -164,14 +164,18 @@ def report(table, nets, sections=None):
             for _ in range(2):
                 step()
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(5):
+            # host clock per step; the median, since a step of ~30k atoms is short enough for a
+            # host-side stall to dominate a mean
+            ts = []
+            for _ in range(10):
+                t0 = time.perf_counter()
                 step()
-            torch.cuda.synchronize()
-            dt = (time.perf_counter() - t0) / 5
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
             print(json.dumps({"report": "training", "form": form, "derivatives": mode, "boxes": len(boxes),
-                              "atoms": int(offs[-1]), "ms_per_step": dt * 1e3,
-                              "workspace_gb": pot.workspace_bytes / 1e9}), flush=True)
+                              "atoms": int(offs[-1]), "ms_per_step": float(np.median(ts)) * 1e3,
+                              "ms_mean": float(np.mean(ts)) * 1e3, "workspace_gb": pot.workspace_bytes / 1e9}),
+                  flush=True)
             pot.close()
             torch.cuda.empty_cache()
     # second workload: single-element fcc metal, 3.9 A cutoff (the paper's Ni runs: ~1.5M atoms)
@@ -228,6 +232,33 @@ def report(table, nets, sections=None):
             pot.close()
             del x, t
             torch.cuda.empty_cache()
+    # neighbour-list layout of the wave-level passes (padded displacement entries, index entries
+    # with a position gather, compact rows) and the pair-test masks on and off, FP32 and FP64, on
+    # both workloads at full size, with the handle's workspace
+    lay_cases = tuple((wl, form, "layout", v) for wl in ("water", "ni") for form in ("fp32", "fp64")
+                      for v in ("padded", "index", "compact")) if want("layouts") else ()
+    lay_cases += tuple((wl, form, "pair_masks", v) for wl in ("water", "ni") for form in ("fp32", "fp64")
+                       for v in ("on", "off")) if want("pair_masks") else ()
+    boxes = {}
+    for wl, form, what, v in lay_cases:
+        if wl not in boxes:
+            boxes[wl] = synth.water_box(88, 22) if wl == "water" else synth.fcc_box(72, 72)
+        bb = boxes[wl]
+        tb, nt = (table, nets) if wl == "water" else (ni_table, ni_nets)
+        pot = Potential(tb, nt, precision=form, elements=("Ni",) if wl == "ni" else ("H", "O"))
+        if what == "layout":
+            pot.set_list_layout(v)
+        else:
+            pot.set_pair_masks(v == "on")
+        x = torch.tensor(bb.pos, dtype=pot.dtype, device=dev)
+        t = torch.tensor(bb.types, dtype=torch.int32, device=dev)
+        ms, st = time_form(pot, x, t, bb.box, 5, 2)
+        print(json.dumps({"report": what, "workload": wl, "form": form, what: v, "atoms": bb.n_atoms,
+                          "ms_per_step": ms, "stages_ms": st, "workspace_gb": pot.workspace_bytes / 1e9}),
+              flush=True)
+        pot.close()
+        del x, t
+        torch.cuda.empty_cache()
     # one energy+force evaluation with the stored-Jacobian forward (one eighth of the 2M box)
     bb = synth.water_box(44, 22) if want("forward_derivatives") else None
     for mode in (("recompute", "stored") if want("forward_derivatives") else ()):
@@ -328,7 +359,8 @@ def main():
                     help="print only the peaks / size-sweep / training / CPU report lines")
     ap.add_argument("--sections", default=None,
                     help="with --report: comma list of report lines to run (peaks, sweep, training, ni, ni_g9, "
-                         "parallelism, forward_derivatives, md, cpu_baseline, cpu_oracle_full); default all")
+                         "parallelism, layouts, pair_masks, forward_derivatives, md, cpu_baseline, "
+                         "cpu_oracle_full); default all")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB with a plain device copy (for HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -354,8 +386,8 @@ def main():
 
     table, nets = synth.water_table_scaled(), synth.water_nets()
     if args.report:
-        known = {"peaks", "sweep", "training", "ni", "ni_g9", "parallelism", "forward_derivatives", "md",
-                 "cpu_baseline", "cpu_oracle_full"}
+        known = {"peaks", "sweep", "training", "ni", "ni_g9", "parallelism", "layouts", "pair_masks",
+                 "forward_derivatives", "md", "cpu_baseline", "cpu_oracle_full"}
         sections = None if args.sections is None else {x for x in args.sections.split(",") if x}
         if sections is not None and not sections <= known:
             ap.error(f"unknown report sections {sorted(sections - known)}; known: {sorted(known)}")

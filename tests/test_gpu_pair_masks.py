@@ -2,11 +2,13 @@
 decisions, one bit per tested pair in blocks of 32 steps of the pair walk,
 and the force pass reads them instead of testing again.
 
-With masks on (the default) every other GPU test already runs through them;
-these tests add what the default workloads do not reach: many mask blocks
-per centre (a compressed water box, about 170 neighbours and eight blocks
-per atom, and a dense ball where every pair is within rc: over 80 blocks),
-masks on against masks off on the same input, and the argument check."""
+Masks are on by default for rows of at least 64 neighbours, so every water
+test at one wave per centre already runs through them (the fcc metal, 18
+neighbours, does not).  These tests add what the default workloads do not
+reach: many mask blocks per centre (a compressed water box, about 170
+neighbours and eight blocks per atom, and a dense ball where every pair is
+within rc: over 80 blocks), masks on against masks off on the same input,
+and the argument check."""
 import numpy as np
 import pytest
 
