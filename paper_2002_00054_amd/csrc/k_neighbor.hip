@@ -334,34 +334,39 @@ __global__ void __launch_bounds__(256) k_neighbors(const double4* __restrict__ p
         int tot = c_tot[ci];
         // padded row (stride cap), compact row at roff[c], or none (counting pass: nbr null)
         E* row = nbr ? nbr + (roff ? (int64_t)roff[c] : (int64_t)c * cap) : nullptr;
+        // the first element block that starts at or after this tile (blocks
+        // start rarely: only steps that reach one look at them)
+        int nbnd = ntot;
+        for (int e = 1; e < n_el; ++e)
+          if (ebeg[e] >= t0 && ebeg[e] < nbnd) nbnd = ebeg[e];
         for (int u0 = 0; u0 < tl; u0 += WAVE) {
           const int u = u0 + lane;
-          bool pass = false;
-          double dx = 0.0, dy = 0.0, dz = 0.0;
-          int sidx = 0;
-          if (u < tl) {
-            const double4 q = sp[u];
-            sidx = (int)(__double_as_longlong(q.w) & 0xffffffffll);
-            dx = q.x - p.x;
-            dy = q.y - p.y;
-            dz = q.z - p.z;
-            if (!shifted) {
-              dx -= L0 * rint(dx * i0);
-              dy -= L1 * rint(dy * i1);
-              dz -= L2 * rint(dz * i2);
-            }
-            pass = sidx != c && dx * dx + dy * dy + dz * dz < rc2;
+          // every lane reads a staged candidate (the last one past the tile's
+          // end); lanes past the end fail the test
+          const double4 q = sp[min(u, tl - 1)];
+          const int sidx = (int)(__double_as_longlong(q.w) & 0xffffffffll);
+          double dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+          if (!shifted) {
+            dx -= L0 * rint(dx * i0);
+            dy -= L1 * rint(dy * i1);
+            dz -= L2 * rint(dz * i2);
           }
+          const bool pass = u < tl && sidx != c && dx * dx + dy * dy + dz * dz < rc2;
           const unsigned long long msk = __builtin_amdgcn_ballot_w64(pass);
           const int rank = tot + lanes_below(msk);
           const bool keep = pass && rank < cap && row;
           if (keep) row[rank] = make_entry_as<E>(dx, dy, dz, sidx);
           // an element block starting inside this step: passing candidates before it
           const int g0 = t0 + u0;
-          for (int e = 1; e < n_el; ++e) {
-            const int b = ebeg[e] - g0;
-            if (b >= 0 && b < WAVE && lane == 0)
-              c_bnd[ci][e] = tot + __popcll(msk & ((1ull << b) - 1ull));
+          if (g0 + WAVE > nbnd) {
+            int nx = ntot;
+            for (int e = 1; e < n_el; ++e) {
+              const int b = ebeg[e] - g0;
+              if (b >= 0 && b < WAVE && lane == 0)
+                c_bnd[ci][e] = tot + __popcll(msk & ((1ull << b) - 1ull));
+              if (ebeg[e] >= g0 + WAVE && ebeg[e] < nx) nx = ebeg[e];
+            }
+            nbnd = nx;
           }
           tot += __popcll(msk);
         }
