@@ -329,9 +329,9 @@ __global__ void __launch_bounds__(256) k_neighbors(const double4* __restrict__ p
       }
       __syncthreads();
       for (int ci = wv; ci < nbc; ci += 4) {
-        const int c = cidx[ci];
+        const int c = uniform(cidx[ci]);  // the wave's centre: its row address is scalar
         const double4 p = cpos[ci];
-        int tot = c_tot[ci];
+        int tot = uniform(c_tot[ci]);
         // padded row (stride cap), compact row at roff[c], or none (counting pass: nbr null)
         E* row = nbr ? nbr + (roff ? (int64_t)roff[c] : (int64_t)c * cap) : nullptr;
         // the first element block that starts at or after this tile (blocks
@@ -351,11 +351,16 @@ __global__ void __launch_bounds__(256) k_neighbors(const double4* __restrict__ p
             dy -= L1 * rint(dy * i1);
             dz -= L2 * rint(dz * i2);
           }
-          const bool pass = u < tl && sidx != c && dx * dx + dy * dy + dz * dz < rc2;
-          const unsigned long long msk = __builtin_amdgcn_ballot_w64(pass);
+          // the three conditions as separate ballots (each is one compare's
+          // lane mask), combined in scalar registers
+          const unsigned long long msk = __builtin_amdgcn_ballot_w64(u < tl) &
+                                         __builtin_amdgcn_ballot_w64(sidx != c) &
+                                         __builtin_amdgcn_ballot_w64(dx * dx + dy * dy + dz * dz < rc2);
           const int rank = tot + lanes_below(msk);
-          const bool keep = pass && rank < cap && row;
-          if (keep) row[rank] = make_entry_as<E>(dx, dy, dz, sidx);
+          const unsigned long long keep = row ? msk & __builtin_amdgcn_ballot_w64(rank < cap) : 0ull;
+          if (__builtin_amdgcn_inverse_ballot_w64(keep))
+            *reinterpret_cast<E*>(reinterpret_cast<char*>(row) + (unsigned)rank * (unsigned)sizeof(E)) =
+                make_entry_as<E>(dx, dy, dz, sidx);
           // an element block starting inside this step: passing candidates before it
           const int g0 = t0 + u0;
           if (g0 + WAVE > nbnd) {
