@@ -321,7 +321,7 @@ nnp_status nnp_set_list_layout(nnp_handle* h, int layout);
  * Pair-test masks (on = 1, the default; 0 = off).  The force pass of
  * Sec. 3.1 step 3 walks the same neighbour pairs (j, k) as the SF pass and,
  * without masks, repeats its test r_jk < rc on each.  With masks the SF pass
- * stores one bit per tested pair and the force pass reads them.  (The paper's
+ * stores one bit per tested pair and the later passes read them.  (The paper's
  * passes store nothing derived from a pair, Sec. 3.3.)  The workspace is
  * about 8 bytes per 64 pairs: n_atoms * ((m^2 + n_el m) / 64 +
  * n_el (n_el + 1) / 2) * 8 bytes, rounded up to 256-byte blocks per atom, for
@@ -330,8 +330,10 @@ nnp_status nnp_set_list_layout(nnp_handle* h, int layout);
  *  - the pass runs at the wave level with one wave per centre;
  *  - m is at least 64 (shorter rows gain nothing);
  *  - the workspace is at most 16 GiB.
- * nnp_compute_noalloc and the backward's force-adjoint pass never use them.
- * Results equal those without masks up to the rounding of the test itself.
+ * The force-adjoint pass of nnp_backward reads the masks of the SF pass whose
+ * neighbour list it uses (the forward's, when the backward reuses it).
+ * nnp_compute_noalloc never uses them.  Results equal those without masks up
+ * to the rounding of the test itself.
  * on outside {0, 1} is NNP_E_ARG.
  */
 nnp_status nnp_set_pair_masks(nnp_handle* h, int on);

@@ -100,6 +100,8 @@ struct nnp_handle {
   // list's state and capacity, and the neighbour-list builds of the last run
   int list_layout = NNP_LIST_PADDED;     // of the wave-level passes with recomputed derivatives
   int pair_masks = 1;                    // SF pass records its pair tests for the force pass
+  unsigned* fwd_pm = nullptr;            // the masks the last SF pass wrote, and their stride
+  int fwd_pm_stride = 0;                 // (0: none; valid with the forward's list, fwd_valid)
   size_t compact_entries = 0;            // entries of the last compact list
   int fwd_layout = NNP_LIST_PADDED;      // layout of the list the last batch forward left
   double md_skin = 0.0;
@@ -479,6 +481,8 @@ nnp_status prepare(nnp_handle* h, Common& cm, const IO* pos, const int32_t* type
   if ((st = ensure_t(h, "flags", 4, &a.flags))) return st;
   if (!sort) return NNP_OK;
   h->fwd_valid = false;  // the sorted order, neighbour list, G~ and J store are about to change
+  h->fwd_pm = nullptr;   // and so are the pair-test masks
+  h->fwd_pm_stride = 0;
   h->skin_ok = false;    // and the Verlet-skin list with them
   launch_fill_int(a.flags, 4, 0, stream);
   launch_bin_sort<IO>(a, pos, stream);
@@ -740,6 +744,27 @@ bool fwd_reusable(nnp_handle* h, Common& cm, const IO* pos, const int32_t* types
 }
 
 // Buffers of one forward evaluation (sorted order unless stated).
+// Pair-test masks for an SF pass at the wave level (ta.wpc set), when they are
+// switched on and pay (rows of PAIR_MASK_MIN_NEIGHBORS or more) and fit:
+// sets ta.pm and ta.pm_stride, and remembers them for the passes that read
+// them (the force pass, and the backward's force-adjoint pass while the
+// forward's list is reused).
+template <int P>
+nnp_status pair_mask_buffer(nnp_handle* h, int64_t n, TripArgs<P>& ta) {
+  h->fwd_pm = nullptr;
+  h->fwd_pm_stride = 0;
+  if (ta.wpc != 1 || !h->pair_masks || h->arena_on || h->lcap < PAIR_MASK_MIN_NEIGHBORS) return NNP_OK;
+  const int blocks = (pair_step_bound(h->lcap, h->n_el) + 31) / 32;
+  const size_t words = (size_t)n * blocks * WAVE;
+  if (words * sizeof(unsigned) > PAIR_MASK_MAX_BYTES) return NNP_OK;
+  nnp_status st;
+  if ((st = ensure_t(h, "pair_masks", words, &ta.pm))) return st;
+  ta.pm_stride = blocks;
+  h->fwd_pm = ta.pm;
+  h->fwd_pm_stride = blocks;
+  return NNP_OK;
+}
+
 template <int P>
 struct FwdBufs {
   using IO = typename Types<P>::IO;
@@ -805,15 +830,7 @@ nnp_status evaluate(nnp_handle* h, Common& cm, Marks& mk, const FwdBufs<P>& b, i
   if (!store) {
     bool flat = false;
     if ((st = use_flat<P>(h, 0, 1, &flat, &ta.wpc, n))) return st;
-    if (!flat && ta.wpc == 1 && h->pair_masks && !h->arena_on && h->lcap >= PAIR_MASK_MIN_NEIGHBORS) {
-      // one bit per candidate pair, written by the SF pass for the force pass
-      const int blocks = (pair_step_bound(h->lcap, h->n_el) + 31) / 32;
-      const size_t words = (size_t)n * blocks * WAVE;
-      if (words * sizeof(unsigned) <= PAIR_MASK_MAX_BYTES) {
-        if ((st = ensure_t(h, "pair_masks", words, &ta.pm))) return st;
-        ta.pm_stride = blocks;
-      }
-    }
+    if (!flat && (st = pair_mask_buffer<P>(h, n, ta))) return st;
     ta.G = b.G;
     if (flat) launch_flat<P>(0, ta, stream);
     else launch_triplet<P>(0, h->variant, ta, stream);
@@ -1048,6 +1065,7 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
       TripArgs<P> ta = trip_args<P>(h, cm);
       bool flat = false;
       if ((st = use_flat<P>(h, 0, 0, &flat, &ta.wpc, n))) return st;
+      if (!flat && (st = pair_mask_buffer<P>(h, n, ta))) return st;
       ta.G = G;
       if (flat) launch_flat<P>(0, ta, stream);
       else launch_triplet<P>(0, h->variant, ta, stream);
@@ -1074,6 +1092,10 @@ nnp_status backward(nnp_handle* h, int n_struct, const int64_t* offs, const void
     TripArgs<P> ta = trip_args<P>(h, cm);
     bool flat = false;
     if ((st = use_flat<P>(h, 2, 2, &flat, &ta.wpc, n))) return st;
+    if (!flat && ta.wpc == 1 && h->fwd_pm_stride > 0) {  // the SF pass's tests of this list
+      ta.pm = h->fwd_pm;
+      ta.pm_stride = h->fwd_pm_stride;
+    }
     ta.delta = delta;
     ta.V = V;
     if (flat) launch_flat<P>(2, ta, stream);

@@ -87,9 +87,9 @@ struct TripArgs {
   IO* V;                     // JVP: rows [n][LD]
   // Pair-test masks of the one-wave pair walk (wpc 1): the SF pass writes the
   // test of lane l at step s of centre c to bit s % 32 of
-  // pm[(c * pm_stride + s / 32) * 64 + l], the force pass reads them instead
-  // of repeating the r_jk < rc test.  pm_stride = 0: both passes test the
-  // pairs.  pm_stride >= ceil(pair_step_bound(lcap, n_el) / 32).
+  // pm[(c * pm_stride + s / 32) * 64 + l], the force and force-adjoint passes
+  // read them instead of repeating the r_jk < rc test.  pm_stride = 0: every
+  // pass tests the pairs.  pm_stride >= ceil(pair_step_bound(lcap, n_el) / 32).
   unsigned* pm;
   int pm_stride;
 };

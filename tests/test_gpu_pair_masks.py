@@ -105,3 +105,42 @@ def test_pair_masks_argument_errors():
     assert pot._L.nnp_set_pair_masks(pot._h, 2) == -1  # NNP_E_ARG through the C ABI
     assert "on must be" in pot._L.nnp_last_error(pot._h).decode()
     pot.close()
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_backward_reads_the_masks(form):
+    """The force-adjoint pass of nnp_backward reads the pair-test masks: of
+    the forward whose list it reuses (a compute_batch on the same inputs just
+    before), or of its own SF pass (a backward alone).  Both, with masks on,
+    equal masks off to the order of the sums.  (One wave per centre named
+    explicitly: a batch this small would otherwise take two, without masks.)"""
+    import torch
+
+    boxes = [synth.water_box(s, 60 + i) for i, s in enumerate((4, 5, 4, 6))]
+    pos = np.concatenate([b.pos for b in boxes])
+    types = np.concatenate([b.types for b in boxes]).astype(np.int32)
+    offs = np.cumsum([0] + [b.n_atoms for b in boxes])
+    bx = np.stack([b.box for b in boxes])
+    rng = np.random.default_rng(3)
+    gE = rng.normal(size=len(boxes))
+    gF = rng.normal(size=pos.shape)
+    grads = {}
+    for on in (True, False):
+        for reuse in (True, False):
+            pot = make_potential(form)
+            pot.set_parallelism("wave")
+            pot.set_pair_masks(on)
+            x = torch.tensor(pos, dtype=pot.dtype, device="cuda")
+            t = torch.tensor(types, device="cuda")
+            if reuse:
+                pot.compute_batch(x, t, offs, bx)
+            g = pot.backward(x, t, offs, bx, torch.tensor(gE, device="cuda"),
+                             torch.tensor(gF, dtype=pot.dtype, device="cuda"))
+            grads[(on, reuse)] = g.cpu().numpy()
+            pot.close()
+    ref = grads[(False, False)]
+    scale = np.max(np.abs(ref))
+    for key, g in grads.items():
+        d = np.max(np.abs(g - ref)) / scale
+        say("backward", form, "masks", key[0], "reuse", key[1], "max rel diff", d)
+        assert d <= (1e-12 if form == "fp64" else 1e-4), (key, d)
