@@ -202,6 +202,14 @@ __device__ inline int lanes_below(unsigned long long m) {
 __device__ inline double exp_scaled(double x_ln, double /*x_log2*/) { return exp(x_ln); }
 __device__ inline float exp_scaled(float /*x_ln*/, float x_log2) { return __builtin_amdgcn_exp2f(x_log2); }
 
+// floor(a / b) for 0 <= a < 2^21 and b >= 1, given inv = rcp(b) (v_rcp_f32,
+// within 1 ulp): (a + 1/2) / b lies at least 1 / (2b) from an integer, and
+// the float error of (a + 1/2) * inv stays below (a + 1/2) 2^-22 / b, so the
+// truncation is exact.  A few VALU instructions instead of the integer
+// division sequence (about 15).
+__device__ inline unsigned small_div(unsigned a, float inv) { return (unsigned)(((float)a + 0.5f) * inv); }
+__device__ inline unsigned small_mod(unsigned a, unsigned b, float inv) { return a - b * small_div(a, inv); }
+
 __device__ inline float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ inline double rsqrt_t(double s) { return 1.0 / sqrt(s); }
