@@ -250,6 +250,7 @@ __global__ void __launch_bounds__(256) k_neighbors(const double4* __restrict__ p
   const bool shifted = n0 >= 3 && n1 >= 3 && n2 >= 3;
   const int mx = n0 >= 3 ? 3 : n0, my = n1 >= 3 ? 3 : n1, mz = n2 >= 3 ? 3 : n2;
   const int nst = mx * my * mz, nseg = n_el * nst;
+  const float inv_nst = __builtin_amdgcn_rcpf((float)nst);
   int cbeg[MAX_EL], clen[MAX_EL], nc = 0;
   for (int f = 0; f < MAX_EL; ++f) {
     cbeg[f] = 0;
@@ -319,7 +320,7 @@ __global__ void __launch_bounds__(256) k_neighbors(const double4* __restrict__ p
           if (seg_off[m] <= g) a = m; else b = m - 1;
         }
         const int sidx = seg_first[a] + (g - seg_off[a]);
-        const int f = a / nst, o = a - f * nst;
+        const int f = (int)small_div((unsigned)a, inv_nst), o = a - f * nst;  // a < 108
         double4 q = pos4[sidx];
         q.x += seg_shift[o][0];
         q.y += seg_shift[o][1];
