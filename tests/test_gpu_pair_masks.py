@@ -144,3 +144,28 @@ def test_backward_reads_the_masks(form):
         d = np.max(np.abs(g - ref)) / scale
         say("backward", form, "masks", key[0], "reuse", key[1], "max rel diff", d)
         assert d <= (1e-12 if form == "fp64" else 1e-4), (key, d)
+
+
+def test_mask_workspace_and_row_threshold():
+    """Masks take a whole number of 256-byte blocks per atom on water (86
+    neighbours), within the step bound of rows of at most 2 * 86; on the fcc
+    metal (18 neighbours, below the 64 from which they pay) they are not
+    allocated at all."""
+    def workspace(table_nets, b, on):
+        pot = make_potential("fp32", *table_nets) if table_nets else make_potential("fp32")
+        pot.set_pair_masks(on)
+        run(pot, b)
+        ws = pot.workspace_bytes
+        pot.close()
+        return ws
+
+    b = synth.water_box(16, 12)
+    extra = workspace(None, b, True) - workspace(None, b, False)
+    per_atom = extra / b.n_atoms
+    say("mask workspace per atom (B)", per_atom)
+    assert extra > 0 and extra % (256 * b.n_atoms) == 0
+    m = 2 * 86
+    assert per_atom <= 256 * (((m * m + 2 * m + 63) // 64 + 3 + 31) // 32)
+    f = synth.fcc_box(8, 2)
+    tn = (synth.ni_table_scaled(), synth.ni_nets())
+    assert workspace(tn, f, True) == workspace(tn, f, False)
