@@ -155,24 +155,34 @@ __device__ inline int lane_id() { return __lane_id(); }
 // lanes; three row shifts finish the sum within each aligned group of 8.
 template <class T>
 __device__ inline T shfl_xor_t(T v, int m) { return __shfl_xor(v, m); }
+// Eight per-lane values summed over the wave: the total of value
+// (lane & 32 ? 4 : 0) + (lane & 16 ? 2 : 0) + (lane & 8 ? 1 : 0) is returned
+// in the lanes with (lane & 7) == 7.
+template <class Acc>
+__device__ inline Acc wave_sum8(const Acc (&v)[8], int lane) {
+  const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
+  Acc a[4], b[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) a[i] = (h32 ? v[i + 4] : v[i]) + shfl_xor_t(h32 ? v[i] : v[i + 4], 32);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) b[i] = (h16 ? a[i + 2] : a[i]) + shfl_xor_t(h16 ? a[i] : a[i + 2], 16);
+  Acc c = (h8 ? b[1] : b[0]) + dpp_shift<0x128>(h8 ? b[0] : b[1]);  // row_ror:8 = lane ^ 8
+  c += dpp_shift<0x111>(c);                                          // row_shr:1
+  c += dpp_shift<0x112>(c);                                          // row_shr:2
+  c += dpp_shift<0x114>(c);                                          // row_shr:4
+  return c;
+}
+__device__ inline int wave_sum8_index(int lane) { return ((lane >> 3) & 4) | ((lane >> 3) & 2) | ((lane >> 3) & 1); }
+
 template <class Acc, int K>
 __device__ inline void wave_sum_many(const Acc (&x)[K], Acc* out, int lane) {
-  const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
-  const int vi = (h32 ? 4 : 0) + (h16 ? 2 : 0) + (h8 ? 1 : 0);
+  const int vi = wave_sum8_index(lane);
 #pragma unroll
   for (int g0 = 0; g0 < K; g0 += 8) {
     Acc v[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = g0 + i < K ? x[g0 + i] : Acc(0);
-    Acc a[4], b[2];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = (h32 ? v[i + 4] : v[i]) + shfl_xor_t(h32 ? v[i] : v[i + 4], 32);
-#pragma unroll
-    for (int i = 0; i < 2; ++i) b[i] = (h16 ? a[i + 2] : a[i]) + shfl_xor_t(h16 ? a[i] : a[i + 2], 16);
-    Acc c = (h8 ? b[1] : b[0]) + dpp_shift<0x128>(h8 ? b[0] : b[1]);  // row_ror:8 = lane ^ 8
-    c += dpp_shift<0x111>(c);                                          // row_shr:1
-    c += dpp_shift<0x112>(c);                                          // row_shr:2
-    c += dpp_shift<0x114>(c);                                          // row_shr:4
+    const Acc c = wave_sum8(v, lane);
     if ((lane & 7) == 7 && g0 + vi < K) out[g0 + vi] = c;
   }
 }
