@@ -561,7 +561,6 @@ TripArgs<P> trip_args(nnp_handle* h, Common& cm) {
   t.n = cm.B.n;
   t.cap = h->cap;
   t.lcap = h->lcap;
-  t.n_cls = h->n_el * (h->n_el + 1) / 2;
   t.pos4 = cm.bin.pos4;
   t.nbr = reinterpret_cast<const typename Vec4<typename Types<P>::T>::type*>(cm.nbr);
   t.idx = cm.idx;
@@ -634,9 +633,8 @@ nnp_status use_flat(nnp_handle* h, int mode_a, int mode_b, bool* flat, int* wpc 
   *flat = h->parallelism == NNP_PAR_THREAD || h->has_wide;
   if (*flat) return NNP_OK;
   auto lds_of = [&](int k) {
-    const int ncls = h->n_el * (h->n_el + 1) / 2;
-    return std::max(triplet_lds_bytes<P>(mode_a, h->variant, h->lcap, ncls, k),
-                    triplet_lds_bytes<P>(mode_b, h->variant, h->lcap, ncls, k));
+    return std::max(triplet_lds_bytes<P>(mode_a, h->variant, h->lcap, k),
+                    triplet_lds_bytes<P>(mode_b, h->variant, h->lcap, k));
   };
   const size_t lds = lds_of(w);
   if (lds <= lds_limit()) return NNP_OK;

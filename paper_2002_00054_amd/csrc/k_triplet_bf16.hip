@@ -4,5 +4,5 @@
 
 namespace nnp {
 template void launch_triplet<P_BF16>(int, int, const TripArgs<P_BF16>&, hipStream_t);
-template size_t triplet_lds_bytes<P_BF16>(int, int, int, int, int);
+template size_t triplet_lds_bytes<P_BF16>(int, int, int, int);
 }  // namespace nnp

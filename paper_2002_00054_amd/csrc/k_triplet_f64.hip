@@ -4,5 +4,5 @@
 
 namespace nnp {
 template void launch_triplet<P_FP64>(int, int, const TripArgs<P_FP64>&, hipStream_t);
-template size_t triplet_lds_bytes<P_FP64>(int, int, int, int, int);
+template size_t triplet_lds_bytes<P_FP64>(int, int, int, int);
 }  // namespace nnp

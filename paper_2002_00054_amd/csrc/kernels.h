@@ -72,7 +72,6 @@ struct TripArgs {
   int64_t n;                 // sorted atoms
   int cap;                   // neighbour slots per atom (row stride of nbr)
   int lcap;                  // LDS capacity: >= the most neighbours of any atom
-  int n_cls;                 // element-pair classes, n_el (n_el + 1) / 2
   const double4* pos4;
   const typename Vec4<T>::type* nbr;  // [n][cap] (dx, dy, dz, j) entries (null with idx)
   const int* idx;            // or [n][cap] neighbour indices alone (wave-level passes only)
@@ -111,7 +110,7 @@ void launch_triplet(int mode, int ne, const TripArgs<P>& a, hipStream_t stream);
 template <int P>
 void launch_flat(int mode, const TripArgs<P>& a, hipStream_t stream);
 template <int P>
-size_t triplet_lds_bytes(int mode, int variant, int lcap, int n_cls, int wpc);
+size_t triplet_lds_bytes(int mode, int ne, int lcap, int wpc);
 
 // ------------------------------------------------- stored-Jacobian form
 // J holds, for every centre c and neighbour slot t (entry e = c * cap + t),
